@@ -1,0 +1,293 @@
+/*
+ * oracle.c -- FP64 reference for the general strided tensor contraction.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * What it computes (Approach, "Supporting tensor computations": the
+ * block-scatter tensor-to-matrix mapping lets matrix algorithms run directly
+ * on tensors; Introduction, "Challenges": tensor work without explicit
+ * conversion between tensors and matrices; Approach, "Variations on
+ * functionality": transposition expressed purely through strides).  The paper
+ * gives no formula, so the oracle writes out the plain definition of a
+ * labelled contraction over strided storage:
+ *
+ *     C[c] <- alpha * sum_{s} A[addr_A(c,s)] * B[addr_B(c,s)] + beta * C[c]
+ *
+ * for every multi-index c over C's labels, where s runs over every label that
+ * appears in A or B but not in C, and the address of an element is
+ * base + sum_d index(label_d) * stride_d.  These are einsum semantics: a label
+ * in all three tensors acts as a batch index, a label only in A (or only in
+ * B) is summed inside the product, and a label repeated within A or B selects
+ * a diagonal.  The library implements the classical case (every label in
+ * exactly two tensors); the wider semantics here pin later extensions.
+ *
+ * Conventions (the paper is silent; readings listed with the design notes):
+ *   - beta == 0: C is not read (BLAS convention), so NaN in C0 does not leak.
+ *   - alpha == 0: A and B are not read.
+ *   - An empty sum (a summed label of extent 0) contributes 0.
+ *   - Summation is sequential in odometer order (first summed label
+ *     fastest), in FP64, optionally Neumaier-compensated.
+ *   - Optionally emits D[c] = |alpha| * sum_s |A*B| + |beta| * |C0[c]|, the
+ *     componentwise condition tensor used by the error bounds.
+ *   - split == 1 forms each product from the bf16 hi/lo split of the two
+ *     operands (mixed precision, Introduction, "Challenges", and "Supporting
+ *     new and mixed precisions"): hi = RNE_bf16(x), lo = RNE_bf16(x - hi),
+ *     product = hi_a*hi_b + hi_a*lo_b + lo_a*hi_b, each term exact in FP64.
+ *     This is the split-exact reference for the bf16x3 path.
+ *
+ * Built with -O2 -fopenmp -ffp-contract=off and no fast-math, so results are
+ * reproducible on any x86-64 host.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_MAX_RANK 8
+#define ORACLE_MAX_LABELS (3 * ORACLE_MAX_RANK)
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_ARG (-1)
+#define ORACLE_ERR_SHAPE (-2)
+#define ORACLE_ERR_LABEL (-3)
+
+typedef struct {
+  int32_t rank;
+  const int64_t *extents;
+  const int64_t *strides;
+  const int32_t *labels;
+} oracle_tensor;
+
+/* Round a float to the nearest bfloat16 value, ties to even, by keeping the
+ * top 16 bits of its IEEE-754 binary32 encoding after adding half an ulp of
+ * the kept part (plus one when the kept part is odd).  NaN stays NaN. */
+static float bf16_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, sizeof u);
+  if ((u & 0x7f800000u) == 0x7f800000u) {
+    if (u & 0x007fffffu) u |= 0x00400000u; /* keep NaN a NaN after truncation */
+    u &= 0xffff0000u;
+  } else {
+    uint32_t keep_odd = (u >> 16) & 1u;
+    u += 0x7fffu + keep_odd;
+    u &= 0xffff0000u;
+  }
+  float r;
+  memcpy(&r, &u, sizeof r);
+  return r;
+}
+
+void oracle_bf16_rne(const float *in, float *out, int64_t n) {
+  for (int64_t i = 0; i < n; ++i) out[i] = bf16_rne(in[i]);
+}
+
+/* One contraction problem after label analysis. */
+typedef struct {
+  int nlab;                              /* distinct labels */
+  int32_t lab[ORACLE_MAX_LABELS];        /* label values */
+  int64_t ext[ORACLE_MAX_LABELS];        /* extent of each label */
+  int64_t sA[ORACLE_MAX_LABELS];         /* A stride of each label (sum over repeats) */
+  int64_t sB[ORACLE_MAX_LABELS];
+  int nout;                              /* C's modes, in C's order */
+  int out_lab[ORACLE_MAX_RANK];          /* label slot of C mode d */
+  int64_t out_stride[ORACLE_MAX_RANK];   /* C stride of mode d */
+  int nsum;                              /* summed labels */
+  int sum_lab[ORACLE_MAX_LABELS];        /* label slot of summed label */
+  int64_t nentries;                      /* number of C entries */
+} problem;
+
+static int find_or_add(problem *p, int32_t label, int64_t extent) {
+  for (int i = 0; i < p->nlab; ++i) {
+    if (p->lab[i] == label) return p->ext[i] == extent ? i : -2;
+  }
+  p->lab[p->nlab] = label;
+  p->ext[p->nlab] = extent;
+  p->sA[p->nlab] = 0;
+  p->sB[p->nlab] = 0;
+  return p->nlab++;
+}
+
+static int check_tensor(const oracle_tensor *t) {
+  if (!t) return ORACLE_ERR_ARG;
+  if (t->rank < 0 || t->rank > ORACLE_MAX_RANK) return ORACLE_ERR_ARG;
+  if (t->rank > 0 && (!t->extents || !t->strides || !t->labels)) return ORACLE_ERR_ARG;
+  for (int d = 0; d < t->rank; ++d)
+    if (t->extents[d] < 0) return ORACLE_ERR_ARG;
+  return ORACLE_OK;
+}
+
+static int analyse(const oracle_tensor *A, const oracle_tensor *B, const oracle_tensor *C,
+                   problem *p) {
+  int rc;
+  if ((rc = check_tensor(A)) || (rc = check_tensor(B)) || (rc = check_tensor(C))) return rc;
+  memset(p, 0, sizeof *p);
+  /* C's labels first, each exactly once. */
+  for (int d = 0; d < C->rank; ++d) {
+    for (int e = 0; e < d; ++e)
+      if (C->labels[e] == C->labels[d]) return ORACLE_ERR_LABEL;
+    int slot = find_or_add(p, C->labels[d], C->extents[d]);
+    p->out_lab[d] = slot;
+    p->out_stride[d] = C->strides[d];
+  }
+  p->nout = C->rank;
+  for (int d = 0; d < A->rank; ++d) {
+    int slot = find_or_add(p, A->labels[d], A->extents[d]);
+    if (slot == -2) return ORACLE_ERR_SHAPE;
+    p->sA[slot] += A->strides[d];
+  }
+  for (int d = 0; d < B->rank; ++d) {
+    int slot = find_or_add(p, B->labels[d], B->extents[d]);
+    if (slot == -2) return ORACLE_ERR_SHAPE;
+    p->sB[slot] += B->strides[d];
+  }
+  /* Every output label must come from an input. */
+  for (int d = 0; d < C->rank; ++d) {
+    int32_t l = C->labels[d];
+    int found = 0;
+    for (int e = 0; e < A->rank; ++e) found |= (A->labels[e] == l);
+    for (int e = 0; e < B->rank; ++e) found |= (B->labels[e] == l);
+    if (!found) return ORACLE_ERR_LABEL;
+  }
+  /* Summed labels: everything that is not an output label, in order of
+   * first appearance (A, then B). */
+  p->nsum = 0;
+  for (int i = C->rank; i < p->nlab; ++i) p->sum_lab[p->nsum++] = i;
+  p->nentries = 1;
+  for (int d = 0; d < C->rank; ++d) p->nentries *= C->extents[d];
+  return ORACLE_OK;
+}
+
+typedef struct {
+  double sum, comp, abssum;
+} accum;
+
+static void acc_add(accum *a, double t, int compensated) {
+  if (compensated) {
+    double s = a->sum + t;
+    if (fabs(a->sum) >= fabs(t))
+      a->comp += (a->sum - s) + t;
+    else
+      a->comp += (t - s) + a->sum;
+    a->sum = s;
+  } else {
+    a->sum += t;
+  }
+}
+
+/* Sum over the summed labels for one output entry whose label values are in
+ * idx[] (output slots filled, summed slots overwritten here). */
+static void one_entry(const problem *p, int64_t *idx, const double *a, const double *b,
+                      int split, int compensated, accum *out) {
+  accum acc = {0.0, 0.0, 0.0};
+  int64_t terms = 1;
+  for (int s = 0; s < p->nsum; ++s) terms *= p->ext[p->sum_lab[s]];
+  for (int s = 0; s < p->nsum; ++s) idx[p->sum_lab[s]] = 0;
+  for (int64_t t = 0; t < terms; ++t) {
+    int64_t offA = 0, offB = 0;
+    for (int l = 0; l < p->nlab; ++l) {
+      offA += idx[l] * p->sA[l];
+      offB += idx[l] * p->sB[l];
+    }
+    double x = a[offA], y = b[offB];
+    acc.abssum += fabs(x * y);
+    if (split) {
+      float xf = (float)x, yf = (float)y;
+      float xh = bf16_rne(xf), yh = bf16_rne(yf);
+      float xl = bf16_rne(xf - xh), yl = bf16_rne(yf - yh);
+      acc_add(&acc, (double)xh * (double)yh, compensated);
+      acc_add(&acc, (double)xh * (double)yl, compensated);
+      acc_add(&acc, (double)xl * (double)yh, compensated);
+    } else {
+      acc_add(&acc, x * y, compensated);
+    }
+    /* odometer step, first summed label fastest */
+    for (int s = 0; s < p->nsum; ++s) {
+      int l = p->sum_lab[s];
+      if (++idx[l] < p->ext[l]) break;
+      idx[l] = 0;
+    }
+  }
+  *out = acc;
+}
+
+static double finish(const accum *acc, double alpha, double beta, double c0, int compensated) {
+  double ab = compensated ? acc->sum + acc->comp : acc->sum;
+  double r = 0.0;
+  if (alpha != 0.0) r = alpha * ab;
+  if (beta != 0.0) r = r + beta * c0;
+  return r;
+}
+
+/* Full contraction, result written into c (which holds C0 on entry) at C's
+ * strides.  d, if not NULL, receives the condition tensor at C's strides. */
+int oracle_contract(double alpha, const oracle_tensor *A, const double *a,
+                    const oracle_tensor *B, const double *b, double beta,
+                    const oracle_tensor *C, double *c, double *d, int split,
+                    int compensated, int nthreads) {
+  problem p;
+  int rc = analyse(A, B, C, &p);
+  if (rc) return rc;
+  if (!c || (alpha != 0.0 && (!a || !b))) return ORACLE_ERR_ARG;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+  for (int64_t e = 0; e < p.nentries; ++e) {
+    int64_t idx[ORACLE_MAX_LABELS];
+    memset(idx, 0, sizeof idx);
+    /* column-major odometer digits of entry e over C's modes */
+    int64_t rem = e, offC = 0;
+    for (int m = 0; m < p.nout; ++m) {
+      int64_t ext = p.ext[p.out_lab[m]];
+      idx[p.out_lab[m]] = rem % ext;
+      rem /= ext;
+      offC += idx[p.out_lab[m]] * p.out_stride[m];
+    }
+    accum acc = {0.0, 0.0, 0.0};
+    if (alpha != 0.0) one_entry(&p, idx, a, b, split, compensated, &acc);
+    double c0 = (beta != 0.0) ? c[offC] : 0.0;
+    double r = finish(&acc, alpha, beta, c0, compensated);
+    if (d) d[offC] = fabs(alpha) * acc.abssum + fabs(beta) * fabs(c0);
+    c[offC] = r;
+  }
+  return ORACLE_OK;
+}
+
+/* Selected entries only: cidx holds n multi-indices over C's modes (row-major
+ * n x rank).  C0 is read from c0 at C's strides (only when beta != 0); the
+ * results go to out[i] (and the condition numbers to dout[i] if not NULL). */
+int oracle_contract_entries(double alpha, const oracle_tensor *A, const double *a,
+                            const oracle_tensor *B, const double *b, double beta,
+                            const oracle_tensor *C, const double *c0,
+                            const int64_t *cidx, int64_t n, double *out, double *dout,
+                            int split, int compensated, int nthreads) {
+  problem p;
+  int rc = analyse(A, B, C, &p);
+  if (rc) return rc;
+  if (n < 0 || (n > 0 && (!cidx || !out))) return ORACLE_ERR_ARG;
+  if (beta != 0.0 && n > 0 && !c0) return ORACLE_ERR_ARG;
+  if (alpha != 0.0 && (!a || !b)) return ORACLE_ERR_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    for (int m = 0; m < p.nout; ++m) {
+      int64_t v = cidx[i * p.nout + m];
+      if (v < 0 || v >= p.ext[p.out_lab[m]]) return ORACLE_ERR_ARG;
+    }
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t idx[ORACLE_MAX_LABELS];
+    memset(idx, 0, sizeof idx);
+    int64_t offC = 0;
+    for (int m = 0; m < p.nout; ++m) {
+      idx[p.out_lab[m]] = cidx[i * p.nout + m];
+      offC += idx[p.out_lab[m]] * p.out_stride[m];
+    }
+    accum acc = {0.0, 0.0, 0.0};
+    if (alpha != 0.0) one_entry(&p, idx, a, b, split, compensated, &acc);
+    double cv = (beta != 0.0) ? c0[offC] : 0.0;
+    out[i] = finish(&acc, alpha, beta, cv, compensated);
+    if (dout) dout[i] = fabs(alpha) * acc.abssum + fabs(beta) * fabs(cv);
+  }
+  return ORACLE_OK;
+}

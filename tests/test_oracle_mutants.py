@@ -1,0 +1,76 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each mutant is a one-line textual change to ``oracle/oracle.c`` of the kind a
+careless rewrite could make (a dropped term, a wrong sign, a wrong stride or
+index, a transposed operand, a wrong rounding rule).  The mutant is compiled
+on the CPU into a temporary library and the pin tests of ``test_oracle.py``
+are run against it; at least one of them must fail.  Nothing here touches the
+GPU or the HIP library."""
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = [
+    ("drop beta term", "if (beta != 0.0) r = r + beta * c0;", "if (beta != 0.0) r = r;"),
+    ("compensation sign", "a->comp += (a->sum - s) + t;", "a->comp += (a->sum - s) - t;"),
+    ("compensation dropped at the end", "double ab = compensated ? acc->sum + acc->comp : acc->sum;",
+     "double ab = acc->sum;"),
+    ("B addressed with A's strides", "offB += idx[l] * p->sB[l];", "offB += idx[l] * p->sA[l];"),
+    ("odometer stops one short", "if (++idx[l] < p->ext[l]) break;",
+     "if (++idx[l] < p->ext[l] - 1) break;"),
+    ("diagonal strides overwritten", "p->sA[slot] += A->strides[d];", "p->sA[slot] = A->strides[d];"),
+    ("split drops lo*hi", "      acc_add(&acc, (double)xl * (double)yh, compensated);\n", "\n"),
+    ("split keeps lo*lo instead of hi*lo",
+     "acc_add(&acc, (double)xh * (double)yl, compensated);",
+     "acc_add(&acc, (double)xl * (double)yl, compensated);"),
+    ("bf16 truncation instead of RNE", "u += 0x7fffu + keep_odd;", "u += 0u;"),
+    ("bf16 ties away from zero", "u += 0x7fffu + keep_odd;", "u += 0x8000u;"),
+    ("C0 read when beta == 0", "double c0 = (beta != 0.0) ? c[offC] : 0.0;",
+     "double c0 = c[offC];"),
+    ("alpha scales C0", "if (beta != 0.0) r = r + beta * c0;", "if (beta != 0.0) r = r + alpha * c0;"),
+    ("condition tensor signed", "acc.abssum += fabs(x * y);", "acc.abssum += x * y;"),
+    ("output digits row-major", "idx[p.out_lab[m]] = rem % ext;\n      rem /= ext;",
+     "idx[p.out_lab[m]] = rem % ext;\n      rem /= (m == 0 ? 1 : ext);"),
+    ("alpha ignored", "if (alpha != 0.0) r = alpha * ab;", "if (alpha != 0.0) r = ab;"),
+]
+
+CHECKS = [
+    lambda: [pins.test_bruteforce_integer_exact(None, s) for s in range(24)],
+    lambda: [pins.test_bruteforce_real(None, s) for s in range(6)],
+    lambda: pins.test_kronecker_delta_closed_form(None),
+    lambda: pins.test_all_ones_closed_form(None),
+    lambda: pins.test_ones_times_random_is_marginal(None),
+    lambda: [pins.test_agrees_with_permuted_gemm(None, s) for s in range(4)],
+    lambda: pins.test_permuted_gemm_integer_exact(None),
+    lambda: pins.test_blas_conventions_nan(None),
+    lambda: pins.test_empty_sum_and_empty_output(None),
+    lambda: pins.test_compensated_summation(None),
+    lambda: pins.test_condition_tensor_mixed_signs(None),
+    lambda: pins.test_bf16_rne_matches_torch(None),
+    lambda: pins.test_split_reference_matches_library_split(None),
+    lambda: pins.test_split_exact_when_inputs_are_bf16(None),
+    lambda: pins.test_golden_fixtures(None),
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, monkeypatch, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor not unique/present: " + name
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(old, new))
+    lib_path = oracle.build(force=True, src=str(mpath), out=str(tmp_path / "libmutant.so"))
+    lib = oracle.load(lib_path)
+    monkeypatch.setattr(oracle, "load", lambda path=None: lib)
+    failures = 0
+    for chk in CHECKS:
+        try:
+            chk()
+        except (AssertionError, oracle.OracleError):
+            failures += 1
+    assert failures > 0, "no pin caught mutant: " + name
