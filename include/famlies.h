@@ -1,0 +1,175 @@
+/*
+ * famlies.h -- C ABI of the MI355X (gfx950) strided tensor-contraction library.
+ *
+ * Operation (Approach, "Supporting tensor computations": the block-scatter
+ * tensor-to-matrix mapping applies matrix algorithms directly to tensors
+ * through indexing vectors; Introduction, "Challenges": tensor work fused
+ * with the matrix multiplication instead of explicit tensor/matrix
+ * conversion; Approach, "Variations on functionality": transposition by
+ * swapping strides):
+ *
+ *     C[c] <- alpha * sum_p A[a(c,p)] * B[b(c,p)] + beta * C[c]
+ *
+ * over labelled modes.  Every label appears in exactly two of A, B, C: a
+ * label in A and C is a row ("I") mode, in B and C a column ("J") mode, in A
+ * and B a contracted ("P") mode.  The element with multi-index idx of a
+ * tensor lives at  base + sum_d idx[d] * strides[d]  (strides in elements,
+ * any sign; zero allowed for A and B).  The descriptor shape follows the
+ * labelled-mode tensor interfaces the paper points to (TAPP, Approach,
+ * "Supporting tensor computations"; Girder 4 project plans).
+ *
+ * Conventions:
+ *   - beta == 0: C is not read (NaN in C0 does not propagate).
+ *     alpha == 0: A and B are not read.
+ *   - An extent of 0 in C makes the call a no-op; an extent of 0 in a
+ *     contracted mode gives C = beta * C.
+ *   - Rank-0 tensors (scalars) are allowed.
+ *   - FAMLIES_F32 rounds alpha and beta to float once.  The bf16x3 compute
+ *     mode keeps them in double and applies them in double.
+ *   - Results are deterministic run to run (no floating-point atomics).
+ *
+ * Errors: every call returns a famlies_status; nothing aborts or throws
+ * across the ABI.  famlies_last_error() returns a thread-local message for
+ * the last failing call on the calling thread (valid until the next call).
+ *
+ * Ownership: the caller owns all tensor memory (device memory for data,
+ * host memory for descriptors).  Descriptor arrays are copied during
+ * planning and may be freed afterwards.  A plan owns its device copies of
+ * the indexing vectors and any split-K workspace; famlies_execute and
+ * famlies_batch_execute allocate nothing and never synchronise, so they may
+ * be captured into a HIP graph.  A handle must outlive its plans.
+ *
+ * Streams are passed as void* (a hipStream_t; NULL = the default stream).
+ */
+#ifndef FAMLIES_H
+#define FAMLIES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t famlies_status;
+
+#define FAMLIES_OK 0
+#define FAMLIES_ERR_INVALID_ARG (-1)    /* null pointer, rank < 0 or > 8, negative extent, bad enum */
+#define FAMLIES_ERR_SHAPE_MISMATCH (-2) /* one label with two different extents */
+#define FAMLIES_ERR_LABEL (-3)          /* C label in neither A nor B, or repeated in C */
+#define FAMLIES_ERR_UNSUPPORTED (-4)    /* valid einsum form not implemented (see below) */
+#define FAMLIES_ERR_ALIAS (-5)          /* C not injective, or C's span overlaps A's/B's */
+#define FAMLIES_ERR_ALIGN (-6)          /* data pointer not aligned to its element size */
+#define FAMLIES_ERR_ALLOC (-7)          /* device allocation failed */
+#define FAMLIES_ERR_DEVICE (-8)         /* a HIP error (pending errors are reported, not cleared) */
+
+#define FAMLIES_MAX_RANK 8
+
+/* Element types of A, B and C (all three share one type). */
+#define FAMLIES_F64 1
+#define FAMLIES_F32 2
+
+/* Compute modes.  NATIVE computes in the element type (FP64 or FP32 MFMA).
+ * BF16X3 (FAMLIES_F32 only) splits every operand x into hi = RNE_bf16(x) and
+ * lo = RNE_bf16(x - hi) while staging tiles, accumulates hi*hi and
+ * hi*lo + lo*hi on BF16 MFMA in FP32, and combines them with alpha, beta
+ * and C in FP64 before storing FP32 (mixed precision: Introduction,
+ * "Challenges"; "Supporting new and mixed precisions"; the split sits in
+ * the packing step as the paper's footnote on forming T*A^T inside the
+ * packing of B does for another transform). */
+#define FAMLIES_NATIVE 0
+#define FAMLIES_BF16X3 1
+
+typedef struct famlies_handle_s *famlies_handle;
+typedef struct famlies_plan_s *famlies_plan;
+
+/* A labelled strided tensor.  extents, strides and labels each hold `rank`
+ * entries (they may be NULL when rank == 0). */
+typedef struct {
+  int32_t rank;
+  const int64_t *extents;
+  const int64_t *strides;
+  const int32_t *labels;
+} famlies_tensor;
+
+/* What the planner decided (host-side summary of a plan). */
+typedef struct {
+  int64_t m, n, k;          /* GEMM sizes: products of I, J and P extents */
+  int32_t swapped;          /* 1 when the kernel runs C^T = B^T A^T, so that C's
+                               smallest-stride mode lies along the kernel's N */
+  int32_t x_kfast, y_kfast; /* 1 when the kernel's left (X) / right (Y) operand
+                               is gathered along its contracted modes */
+  int32_t n_i, n_j, n_p;    /* mode groups after dropping extent-1 modes and fusing */
+  int32_t tile_m, tile_n, tile_k;
+  int32_t split_k;          /* number of K slices (1 = none) */
+  int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
+  int32_t kernel;           /* internal kernel variant id */
+  double flops;             /* 2*m*n*k */
+} famlies_plan_info;
+
+/* Create a handle bound to HIP device `device` (reads the tile table named by
+ * the FAMLIES_TUNE_TABLE environment variable if set). */
+famlies_status famlies_create(famlies_handle *out, int device);
+famlies_status famlies_destroy(famlies_handle h);
+
+/* Plan C = alpha*A.B + beta*C for one contraction (steps: validate and
+ * classify labels; drop extent-1 modes, order and fuse mode groups; choose
+ * the orientation and gather directions; build the block-scatter indexing
+ * vectors -- the "indexing vectors" of the paper's block-scatter mapping --
+ * and upload them; choose tile shape and split-K).  dtype is FAMLIES_F64 or
+ * FAMLIES_F32; compute is FAMLIES_NATIVE or (F32 only) FAMLIES_BF16X3.
+ * UNSUPPORTED: a label in all three tensors (batch mode), a label in only A
+ * or only B (trace), or a label repeated within A or B (diagonal). */
+famlies_status famlies_plan_contract(famlies_handle h, famlies_plan *out, int dtype, int compute,
+                                     const famlies_tensor *A, const famlies_tensor *B,
+                                     const famlies_tensor *C);
+
+/* Run a plan on device pointers A, B, C (each the address of the element
+ * with all-zero multi-index) on `stream`.  Checks pointer alignment and that
+ * C's address span does not overlap A's or B's.  Asynchronous. */
+famlies_status famlies_execute(famlies_plan p, double alpha, const void *A, const void *B,
+                               double beta, void *C, void *stream);
+
+famlies_status famlies_plan_destroy(famlies_plan p);
+famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info *out);
+
+/* Host-only dry run of the planner: fills *info and, if offsets != NULL,
+ * writes the six indexing vectors of the kernel view, unpadded and in this
+ * order: X rows (m entries), X contracted (k), Y contracted (k), Y columns
+ * (n), C rows (m), C columns (n); element (m,k) of X is at
+ * X + xrow[m] + xk[k] and so on, where X is A (or B when swapped).
+ * offsets_len must be at least 2m + 2k + 2n.  Touches no device. */
+famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor *A,
+                               const famlies_tensor *B, const famlies_tensor *C,
+                               famlies_plan_info *info, int64_t *offsets, int64_t offsets_len);
+
+/* Batched: n independent contractions (descriptor arrays of length n) of one
+ * dtype, run by one persistent kernel over a device work list of
+ * (problem, tile) items, tile shapes per size class from the handle's tile
+ * table (tiles and orientation as in famlies_plan_contract; each descriptor
+ * obeys the same rules).  Tensors of different problems may share memory
+ * for A and B; C outputs must be disjoint (not checked). */
+famlies_status famlies_batch_plan(famlies_handle h, famlies_plan *out, int dtype, int64_t n,
+                                  const famlies_tensor *A, const famlies_tensor *B,
+                                  const famlies_tensor *C);
+
+/* A_dev, B_dev, C_dev: device arrays of n device pointers each.  One kernel
+ * launch; graph-capturable. */
+famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta,
+                                     const void *const *A_dev, const void *const *B_dev,
+                                     void *const *C_dev, void *stream);
+
+/* Autotune: time the candidate tile shapes on synthetic problems of each
+ * size class on the handle's device and write the table to table_path
+ * (text, one line per class); the handle then uses it.  flags: bit 0 = quick
+ * (fewer repetitions). */
+famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags);
+/* Load a table written by famlies_tune. */
+famlies_status famlies_load_tune_table(famlies_handle h, const char *table_path);
+
+const char *famlies_last_error(void);
+const char *famlies_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FAMLIES_H */

@@ -1,0 +1,383 @@
+// C ABI: handles, plans, planning (tile choice, indexing-vector upload) and
+// execution.  Errors are returned as famlies_status with a thread-local
+// message (graceful error handling and bounds checking: Girder 1, "Code
+// safety").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "famlies.h"
+#include "internal.hpp"
+#include "launch.hpp"
+#include "runtime.hpp"
+
+namespace famlies {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static std::mutex g_live_mu;
+static std::set<const void*> g_live;  // live handles and plans (use-after-destroy check)
+
+void register_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.insert(p);
+}
+void unregister_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.erase(p);
+}
+bool is_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return g_live.count(p) != 0;
+}
+
+famlies_status fail(famlies_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+famlies_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? FAMLIES_ERR_ALLOC : FAMLIES_ERR_DEVICE;
+}
+
+// Make `device` current for the scope, restoring the caller's device after.
+DeviceGuard::DeviceGuard(int device) {
+  ok = hipGetDevice(&prev) == hipSuccess;
+  if (ok && prev != device) ok = hipSetDevice(device) == hipSuccess;
+  else if (ok) prev = -1;
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Step a4: tile shape and split-K.  A tile-table entry for the problem's
+// size class wins; otherwise large tiles for large problems, small tiles when
+// the large ones would leave most CUs idle, and split-K when even that does
+// not fill the chip and K is long.
+TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
+  TileCfg t;
+  const int bk = an.dtype == FAMLIES_F64 ? 16 : 32;
+  t.bk = bk;
+  if (an.M == 0 || an.N == 0 || an.K == 0) return t;
+  if (h && h->table.lookup_plain(an, &t)) return t;
+  const int cus = h ? h->num_cus : 256;
+  const int64_t big = ceil_div(an.M, 128) * ceil_div(an.N, 128);
+  if (big >= cus / 2) {
+    t.bm = t.bn = 128;
+  } else {
+    t.bm = t.bn = 64;
+  }
+  const int64_t tiles = ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn);
+  t.split = 1;
+  if (tiles < cus) {
+    int64_t want = ceil_div(2 * cus, tiles);
+    int64_t maxs = std::max<int64_t>(1, an.K / (2 * bk));
+    t.split = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 64}));
+  }
+  return t;
+}
+
+static void finalize_split(TileCfg* t, int64_t K, int* kchunk) {
+  if (t->split <= 1 || K <= t->bk) {
+    t->split = 1;
+    *kchunk = (int)std::max<int64_t>(K, 1);
+    return;
+  }
+  int64_t chunk = ceil_div(ceil_div(K, t->split), t->bk) * t->bk;
+  t->split = (int)ceil_div(K, chunk);
+  *kchunk = (int)chunk;
+  if (t->split <= 1) {
+    t->split = 1;
+    *kchunk = (int)K;
+  }
+}
+
+static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int kernel,
+                      famlies_plan_info* info) {
+  std::memset(info, 0, sizeof *info);
+  info->m = an.M;
+  info->n = an.N;
+  info->k = an.K;
+  info->swapped = an.swapped;
+  info->x_kfast = an.x_kfast;
+  info->y_kfast = an.y_kfast;
+  info->n_i = (int32_t)an.I.size();
+  info->n_j = (int32_t)an.J.size();
+  info->n_p = (int32_t)an.P.size();
+  info->tile_m = t.bm;
+  info->tile_n = t.bn;
+  info->tile_k = t.bk;
+  info->split_k = t.split;
+  info->index_bits = index_bits;
+  info->kernel = kernel;
+  info->flops = 2.0 * (double)an.M * (double)an.N * (double)an.K;
+}
+
+static int index_bits_for(const Analysis& an) {
+  const int64_t lim = (int64_t)1 << 30;
+  return (an.max_abs_x < lim && an.max_abs_y < lim && an.max_abs_c < lim) ? 32 : 64;
+}
+
+// Upload the six indexing vectors (padded to the tile grid) into one device
+// buffer of OffT.
+template <typename OffT>
+static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp) {
+  const Analysis& an = p->an;
+  std::vector<int64_t> v[6];
+  offsets(an.I, 0, an.M, mp, v[0]);
+  offsets(an.P, 0, an.K, kp, v[1]);
+  offsets(an.P, 1, an.K, kp, v[2]);
+  offsets(an.J, 1, an.N, np, v[3]);
+  offsets(an.I, 2, an.M, mp, v[4]);
+  offsets(an.J, 2, an.N, np, v[5]);
+  size_t total = 0;
+  for (auto& x : v) total += x.size();
+  std::vector<OffT> host(total);
+  size_t pos = 0;
+  for (int i = 0; i < 6; ++i) {
+    p->off_pos[i] = pos;
+    for (int64_t o : v[i]) host[pos++] = (OffT)o;
+  }
+  hipError_t e = hipMalloc(&p->d_off, total * sizeof(OffT));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(indexing vectors)");
+  e = hipMemcpy(p->d_off, host.data(), total * sizeof(OffT), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(indexing vectors)");
+  return FAMLIES_OK;
+}
+
+template <typename OffT>
+static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const void* y, void* c,
+                                 double alpha, double beta) {
+  PlainArgs<OffT> a;
+  const OffT* o = static_cast<const OffT*>(p->d_off);
+  a.x = x;
+  a.y = y;
+  a.c = c;
+  a.xmn = o + p->off_pos[0];
+  a.xk = o + p->off_pos[1];
+  a.yk = o + p->off_pos[2];
+  a.ymn = o + p->off_pos[3];
+  a.cm = o + p->off_pos[4];
+  a.cn = o + p->off_pos[5];
+  a.M = (int32_t)p->an.M;
+  a.N = (int32_t)p->an.N;
+  a.K = (int32_t)p->an.K;
+  a.tiles_m = (int32_t)ceil_div(p->an.M, p->cfg.bm);
+  a.tiles_n = (int32_t)ceil_div(p->an.N, p->cfg.bn);
+  a.splits = p->cfg.split;
+  a.kchunk = p->kchunk;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.work = p->d_work;
+  return a;
+}
+
+}  // namespace famlies
+
+famlies_plan_s::~famlies_plan_s() {
+  if (d_off) (void)hipFree(d_off);
+  if (d_work) (void)hipFree(d_work);
+  if (batch) famlies::destroy_batch(batch);
+}
+
+using namespace famlies;
+
+extern "C" {
+
+const char* famlies_last_error(void) { return g_err.c_str(); }
+
+const char* famlies_version(void) { return "famlies-mi355x 0.1 (gfx950)"; }
+
+famlies_status famlies_create(famlies_handle* out, int device) {
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_create: null output pointer");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_create: no such device");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(FAMLIES_ERR_UNSUPPORTED, std::string("famlies_create: device is ") + prop.gcnArchName +
+                                             ", this library is built for gfx950 only");
+  auto* h = new (std::nothrow) famlies_handle_s();
+  if (!h) return fail(FAMLIES_ERR_ALLOC, "famlies_create: out of host memory");
+  h->device = device;
+  h->num_cus = prop.multiProcessorCount;
+  const char* tt = std::getenv("FAMLIES_TUNE_TABLE");
+  if (tt && *tt) {
+    std::string err;
+    if (!h->table.load(tt, &err)) {
+      delete h;
+      return fail(FAMLIES_ERR_INVALID_ARG, "FAMLIES_TUNE_TABLE: " + err);
+    }
+  }
+  register_live(h);
+  *out = h;
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_destroy(famlies_handle h) {
+  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_destroy: invalid handle");
+  unregister_live(h);
+  delete h;
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tensor* B,
+                               const famlies_tensor* C, famlies_plan_info* info, int64_t* offs,
+                               int64_t offs_len) {
+  if (!info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: null info");
+  Analysis an;
+  std::string err;
+  int st = analyze(dtype, compute, A, B, C, &an, &err);
+  if (st != FAMLIES_OK) return fail(st, err);
+  TileCfg t = choose_tiles(nullptr, an);
+  int kchunk = 0;
+  finalize_split(&t, an.K, &kchunk);
+  fill_info(an, t, index_bits_for(an), 0, info);
+  if (offs) {
+    const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N;
+    if (offs_len < need) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: offsets buffer too short");
+    std::vector<int64_t> v;
+    int64_t pos = 0;
+    const std::vector<Mode>* groups[6] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J};
+    const int which[6] = {0, 0, 1, 1, 2, 2};
+    const int64_t len[6] = {an.M, an.K, an.K, an.N, an.M, an.N};
+    for (int i = 0; i < 6; ++i) {
+      offsets(*groups[i], which[i], len[i], len[i], v);
+      std::copy(v.begin(), v.end(), offs + pos);
+      pos += len[i];
+    }
+  }
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_plan_contract(famlies_handle h, famlies_plan* out, int dtype, int compute,
+                                     const famlies_tensor* A, const famlies_tensor* B,
+                                     const famlies_tensor* C) {
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
+  *out = nullptr;
+  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
+  Analysis an;
+  std::string err;
+  int st = analyze(dtype, compute, A, B, C, &an, &err);
+  if (st != FAMLIES_OK) return fail(st, err);
+  const int64_t lim = ((int64_t)1 << 31) - 1024;
+  if (an.M > lim || an.N > lim || an.K > lim)
+    return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
+  auto* p = new (std::nothrow) famlies_plan_s();
+  if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  p->h = h;
+  p->an = an;
+  p->index_bits = index_bits_for(an);
+  p->cfg = choose_tiles(h, an);
+  if (compute == FAMLIES_BF16X3) {
+    p->cfg.bk = 32;
+    if (!bf16x3_tile_supported(p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
+  } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
+    p->cfg.bm = p->cfg.bn = 128;
+    p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
+  }
+  finalize_split(&p->cfg, an.K, &p->kchunk);
+  const bool empty = an.M == 0 || an.N == 0;
+  if (!empty) {
+    const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
+    const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
+    const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
+    st = p->index_bits == 32 ? upload<int32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
+    if (st != FAMLIES_OK) {
+      delete p;
+      return st;
+    }
+    if (p->cfg.split > 1 && an.K > 0) {
+      const size_t es = compute == FAMLIES_BF16X3 ? 8 : (size_t)an.esize;
+      p->work_bytes = (size_t)p->cfg.split * (size_t)mp * (size_t)np * es;
+      hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
+      if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc(split-K workspace)");
+      }
+    }
+  }
+  register_live(p);
+  *out = p;
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_plan_destroy(famlies_plan p) {
+  if (!p || !is_live(p)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_destroy: invalid plan");
+  unregister_live(p);
+  DeviceGuard dg(p->h->device);
+  delete p;
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info* info) {
+  if (!p || !is_live(p) || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
+  fill_info(p->an, p->cfg, p->index_bits, p->an.compute == FAMLIES_BF16X3 ? 2 : 1, info);
+  return FAMLIES_OK;
+}
+
+static bool overlaps(const void* p, int64_t plo, int64_t phi, const void* q, int64_t qlo, int64_t qhi,
+                     int es) {
+  if (plo > phi || qlo > qhi) return false;
+  const intptr_t a0 = (intptr_t)p + plo * es, a1 = (intptr_t)p + (phi + 1) * es;
+  const intptr_t b0 = (intptr_t)q + qlo * es, b1 = (intptr_t)q + (qhi + 1) * es;
+  return a0 < b1 && b0 < a1;
+}
+
+famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+                               void* C, void* stream) {
+  if (!p || !is_live(p) || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute: invalid plan");
+  const Analysis& an = p->an;
+  if (an.M == 0 || an.N == 0) return FAMLIES_OK;
+  const bool need_ab = alpha != 0.0 && an.K > 0;
+  if (!C || (need_ab && (!A || !B))) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute: null data pointer");
+  const uintptr_t al = (uintptr_t)an.esize - 1;
+  if (((uintptr_t)C & al) || (need_ab && (((uintptr_t)A & al) || ((uintptr_t)B & al))))
+    return fail(FAMLIES_ERR_ALIGN, "famlies_execute: data pointer not aligned to its element size");
+  if (need_ab && (overlaps(C, an.c_lo, an.c_hi, A, an.a_lo, an.a_hi, an.esize) ||
+                  overlaps(C, an.c_lo, an.c_hi, B, an.b_lo, an.b_hi, an.esize)))
+    return fail(FAMLIES_ERR_ALIAS, "famlies_execute: C overlaps A or B");
+  DeviceGuard dg(p->h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the plan's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* x = an.swapped ? B : A;
+  const void* y = an.swapped ? A : B;
+  PlainLaunch L;
+  L.bm = p->cfg.bm;
+  L.bn = p->cfg.bn;
+  L.bk = p->cfg.bk;
+  L.xk = an.x_kfast;
+  L.yk = an.y_kfast;
+  L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
+  hipError_t e;
+  if (an.compute == FAMLIES_BF16X3 && L.kind == PlainLaunch::kMain) {
+    e = p->index_bits == 32 ? launch_bf16x3(make_args<int32_t>(p, x, y, C, alpha, beta), L, s)
+                            : launch_bf16x3(make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
+  } else {
+    e = p->index_bits == 32 ? launch_plain(an.dtype, make_args<int32_t>(p, x, y, C, alpha, beta), L, s)
+                            : launch_plain(an.dtype, make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return FAMLIES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// bf16x3 precision path: FP32 data, products on BF16 MFMA.
+//
+// Each FP32 operand value x is split while it is staged into LDS (the
+// transform sits inside the packing step, as the paper does for T*A^T in its
+// footnote on the sandwiched GEMM C := C - A T A^T):
+//     hi = RNE_bf16(x),   lo = RNE_bf16(x - hi)      (x - hi is exact in FP32)
+// and  x*y ~= hi_x*hi_y + (hi_x*lo_y + lo_x*hi_y), dropping lo_x*lo_y.
+// The hi*hi products accumulate in one FP32 MFMA accumulator, the two cross
+// products in a second; the epilogue combines them with alpha, beta and C in
+// FP64 and stores FP32 (new and mixed precisions: Introduction,
+// "Challenges"; "Supporting new and mixed precisions").
+#include "device.hpp"
+#include "runtime.hpp"
+
+namespace famlies {
+
+// v_mfma_f32_32x32x16_bf16: lane l supplies 8 consecutive contraction
+// entries of row (left) / column (right) l % 32 for contraction group l / 32;
+// the accumulator layout is that of the 32x32 FP32 shape.
+__device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+template <bool KFAST, int BK>
+struct SplitLds {
+  // bf16 row pitch: K-gathered tiles keep 16-byte aligned rows (+8 bf16),
+  // row-gathered tiles use an odd dword pitch (+2 bf16) so that lanes writing
+  // consecutive rows hit different banks.
+  static constexpr int LDK = KFAST ? BK + 8 : BK + 2;
+};
+
+template <typename G, bool KFAST, int LDK>
+__device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo) {
+#pragma unroll
+  for (int j = 0; j < G::E; ++j) {
+    const float x = gg.v[j];
+    const __bf16 h = static_cast<__bf16>(x);
+    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
+    const int idx = KFAST ? (gg.r0 + j * G::RSTEP) * LDK + gg.kk0 : gg.r0 * LDK + gg.kk0 + j * G::KSTEP;
+    hi[idx] = h;
+    lo[idx] = l;
+  }
+}
+
+// 8 consecutive bf16 starting at p (4-byte aligned at least).
+template <bool ALIGN16>
+__device__ __forceinline__ bf16x8 read8(const __bf16* p) {
+  if constexpr (ALIGN16) {
+    return *reinterpret_cast<const bf16x8*>(p);
+  } else {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+    u32x4 w = {q[0], q[1], q[2], q[3]};
+    return __builtin_bit_cast(bf16x8, w);
+  }
+}
+
+template <typename OffT, int BM, int BN, bool XK, bool YK>
+__global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
+  constexpr int BK = 32;
+  using GX = TileGather<float, OffT, BM, BK, XK>;
+  using GY = TileGather<float, OffT, BN, BK, YK>;
+  constexpr int LX = SplitLds<XK, BK>::LDK, LY = SplitLds<YK, BK>::LDK;
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int MB = WTM / 32, NB = WTN / 32;
+  constexpr int XS = BM * LX, YS = BN * LY;      // bf16 elements per tile
+  constexpr int STAGE = 2 * XS + 2 * YS;         // hi and lo of both tiles
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid % 64, wave = tid / 64;
+  const int wm = wave / 2, wn = wave % 2;
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = a.tiles_m * a.tiles_n;
+  const int split = lid / ntiles;
+  const int t = lid % ntiles;
+  const int pm = t % a.tiles_m, pn = t / a.tiles_m;
+  const int m0 = pm * BM, n0 = pn * BN;
+  const int kbeg = split * a.kchunk;
+  const int kend = min(a.K, kbeg + a.kchunk);
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  const float* __restrict__ X = static_cast<const float*>(a.x);
+  const float* __restrict__ Y = static_cast<const float*>(a.y);
+
+  GX gx;
+  GY gy;
+  gx.init(a.xmn, m0, tid);
+  gy.init(a.ymn, n0, tid);
+
+  f32x16 hh[MB][NB], mid[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      hh[i][j] = f32x16{};
+      mid[i][j] = f32x16{};
+    }
+
+  const int g = lane / 32, r = lane % 32;
+  auto stage_store = [&](int buf) {
+    __bf16* base = smem + buf * STAGE;
+    store_split<GX, XK, LX>(gx, base, base + XS);
+    store_split<GY, YK, LY>(gy, base + 2 * XS, base + 2 * XS + YS);
+  };
+  if (nk > 0) {
+    gx.load(X, a.xk, kbeg, kend);
+    gy.load(Y, a.yk, kbeg, kend);
+    stage_store(0);
+    __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int cur = it & 1;
+      const bool more = it + 1 < nk;
+      if (more) {
+        const int kn = kbeg + (it + 1) * BK;
+        gx.load(X, a.xk, kn, kend);
+        gy.load(Y, a.yk, kn, kend);
+      }
+      const __bf16* xh = smem + cur * STAGE;
+      const __bf16* xl = xh + XS;
+      const __bf16* yh = xh + 2 * XS;
+      const __bf16* yl = yh + YS;
+      // lane group g covers k in [16g, 16g + 16) of the slice, in two steps of 8
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        bf16x8 ah[MB], al[MB], bh[NB], bl[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          const int o = (wm * WTM + i * 32 + r) * LX + g * 16 + s * 8;
+          ah[i] = read8<XK>(xh + o);
+          al[i] = read8<XK>(xl + o);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int o = (wn * WTN + j * 32 + r) * LY + g * 16 + s * 8;
+          bh[j] = read8<YK>(yh + o);
+          bl[j] = read8<YK>(yl + o);
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            hh[i][j] = mma_bf16(ah[i], bh[j], hh[i][j]);
+            mid[i][j] = mma_bf16(ah[i], bl[j], mid[i][j]);
+            mid[i][j] = mma_bf16(al[i], bh[j], mid[i][j]);
+          }
+      }
+      if (more) stage_store(cur ^ 1);
+      __syncthreads();
+    }
+  }
+
+  if (a.splits == 1) {
+    float* __restrict__ C = static_cast<float*>(a.c);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + wn * WTN + j * 32 + r;
+      const OffT cn = a.cn[n];
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
+          if (m < a.M && n < a.N) {
+            const OffT idx = a.cm[m] + cn;
+            double v = a.alpha * ((double)hh[i][j][e] + (double)mid[i][j][e]);
+            if (a.beta != 0.0) v += a.beta * (double)C[idx];
+            C[idx] = (float)v;
+          }
+        }
+    }
+  } else {
+    const int ldw = a.tiles_n * BN;
+    double* __restrict__ W = static_cast<double*>(a.work) + (size_t)split * (size_t)(a.tiles_m * BM) * ldw;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + wn * WTN + j * 32 + r;
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
+          W[(size_t)m * ldw + n] = (double)hh[i][j][e] + (double)mid[i][j][e];
+        }
+    }
+  }
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kThreads) void bf16x3_reduce(PlainArgs<OffT> a, int ldw, int rows) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= (int64_t)a.M * a.N) return;
+  const int m = (int)(i / a.N), n = (int)(i % a.N);
+  const double* W = static_cast<const double*>(a.work);
+  const size_t plane = (size_t)rows * ldw;
+  double s = 0.0;
+  for (int k = 0; k < a.splits; ++k) s += W[(size_t)k * plane + (size_t)m * ldw + n];
+  float* C = static_cast<float*>(a.c);
+  const OffT idx = a.cm[m] + a.cn[n];
+  double v = a.alpha * s;
+  if (a.beta != 0.0) v += a.beta * (double)C[idx];
+  C[idx] = (float)v;
+}
+
+template <typename OffT, int BM, int BN>
+static hipError_t launch_b3_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int grid, hipStream_t s) {
+  if (xk && yk)
+    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, true, true>), dim3(grid), dim3(kThreads), 0, s, a);
+  else if (xk)
+    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, true, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  else if (yk)
+    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, false, false>), dim3(grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename OffT>
+static hipError_t launch_b3(const PlainArgs<OffT>& a, const PlainLaunch& L, hipStream_t s) {
+  const int grid = a.tiles_m * a.tiles_n * a.splits;
+  hipError_t e = hipErrorInvalidValue;
+  if (L.bm == 128 && L.bn == 128)
+    e = launch_b3_tile<OffT, 128, 128>(a, L.xk, L.yk, grid, s);
+  else if (L.bm == 64 && L.bn == 64)
+    e = launch_b3_tile<OffT, 64, 64>(a, L.xk, L.yk, grid, s);
+  if (e != hipSuccess || a.splits == 1) return e;
+  const int64_t mn = (int64_t)a.M * a.N;
+  hipLaunchKernelGGL((bf16x3_reduce<OffT>), dim3((int)((mn + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, a, a.tiles_n * L.bn, a.tiles_m * L.bm);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16x3(const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s) {
+  return launch_b3(a, L, s);
+}
+hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {
+  return launch_b3(a, L, s);
+}
+bool bf16x3_tile_supported(int bm, int bn) { return (bm == 128 && bn == 128) || (bm == 64 && bn == 64); }
+
+}  // namespace famlies

@@ -1,0 +1,136 @@
+// Device building blocks of the contraction kernels (gfx950 / CDNA4).
+//
+// Structure follows the paper's GEMM layering (the BLIS refactoring as loops
+// around a micro-kernel with packed operands, Fig. "five loops around the
+// micro-kernel"), re-cut for a GPU: the workgroup grid replaces the outer
+// cache-blocking loops, the block-scatter gather into LDS replaces packing
+// into contiguous panels (Approach, "Supporting tensor computations"), and
+// wave-level MFMA tiles replace the register micro-kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "args.hpp"
+
+namespace famlies {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;  // 4 waves of 64 lanes
+constexpr int kXcds = 8;       // MI355X: 8 XCDs, 32 CUs each
+
+// Workgroups are dealt round-robin to the XCDs (id % 8).  Renumber them so
+// that consecutive logical tile ids land on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_remap(int bid, int total) {
+  int q = total / kXcds, r = total % kXcds;
+  int xcd = bid % kXcds, idx = bid / kXcds;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// MFMA shapes.  In every shape the lane index l selects the row (of the left
+// operand) and the column (of the right operand) as l % BS, and the group
+// l / BS selects the contraction index, the same way for both operands, so
+// any consistent assignment of tile k's to (group, step) is valid.
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {  // v_mfma_f64_16x16x4_f64
+  static constexpr int BS = 16, KG = 4, NACC = 4;
+  using Acc = f64x4;
+  __device__ __forceinline__ static Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of accumulator element r held by lane l (column is l % 16)
+  __device__ __forceinline__ static int row(int l, int r) { return 4 * (l / 16) + r; }
+};
+
+template <>
+struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
+  static constexpr int BS = 32, KG = 2, NACC = 16;
+  using Acc = f32x16;
+  __device__ __forceinline__ static Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int l, int r) {
+    return 8 * (r / 4) + 4 * (l / 32) + (r % 4);
+  }
+};
+
+// Gather of one operand tile (BR rows of the free dimension x BK contracted
+// indices) from strided global memory through the block-scatter indexing
+// vectors into LDS laid out [row][k] with leading dimension LDK.
+//
+// KFAST (the operand's smallest stride is a contracted mode): lanes run along
+// k, each thread owns one k column and E rows.  Otherwise lanes run along the
+// rows, each thread owns one row and E k's; those k's are the same for a whole
+// wave when BR is a multiple of 64, so their offsets are wave-uniform loads.
+// Rows past the problem edge carry offset 0 (a valid address) and only feed
+// accumulator rows that are never stored; k's past the edge load as 0.
+template <typename T, typename OffT, int BR, int BK, bool KFAST>
+struct TileGather {
+  static constexpr int E = BR * BK / kThreads;
+  static constexpr int LDK = KFAST ? BK + 16 / (int)sizeof(T) : BK + 1;
+  static constexpr int RSTEP = kThreads / BK;  // KFAST: row step between a thread's elements
+  static constexpr int KSTEP = kThreads / BR;  // !KFAST: k step between a thread's elements
+  static_assert(E >= 1, "tile too small for the workgroup");
+  static_assert(KFAST ? (kThreads % BK == 0 && BR % RSTEP == 0)
+                      : (kThreads % BR == 0 && BK % KSTEP == 0),
+                "tile shape does not divide the workgroup");
+
+  OffT mn[KFAST ? E : 1];
+  T v[E];
+  int r0, kk0;
+
+  __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
+    if constexpr (KFAST) {
+      kk0 = tid % BK;
+      r0 = tid / BK;
+#pragma unroll
+      for (int j = 0; j < E; ++j) mn[j] = mnoff[tile_r0 + r0 + j * RSTEP];
+    } else {
+      r0 = tid % BR;
+      kk0 = tid / BR;
+      if constexpr (BR % 64 == 0) kk0 = __builtin_amdgcn_readfirstlane(kk0);
+      mn[0] = mnoff[tile_r0 + r0];
+    }
+  }
+
+  __device__ __forceinline__ void load(const T* __restrict__ base, const OffT* __restrict__ koff,
+                                       int k0, int kend) {
+    if constexpr (KFAST) {
+      const int k = k0 + kk0;
+      const OffT ko = koff[k];
+      const bool ok = k < kend;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        T t = base[mn[j] + ko];
+        v[j] = ok ? t : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k = k0 + kk0 + j * KSTEP;
+        const OffT ko = koff[k];
+        T t = base[mn[0] + ko];
+        v[j] = k < kend ? t : T(0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(T* __restrict__ lds) const {
+    if constexpr (KFAST) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lds[(r0 + j * RSTEP) * LDK + kk0] = v[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < E; ++j) lds[r0 * LDK + kk0 + j * KSTEP] = v[j];
+    }
+  }
+};
+
+}  // namespace famlies

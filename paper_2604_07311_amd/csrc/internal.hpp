@@ -1,0 +1,58 @@
+// Host-side data structures shared by the planner, the launchers and the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "famlies.h"
+
+namespace famlies {
+
+// One (possibly fused) mode of a group, with its stride in each operand of
+// the kernel view: X (left, rows M), Y (right, columns N) and C.  A stride is
+// 0 in an operand that does not hold the mode.
+struct Mode {
+  int32_t label;
+  int64_t ext;
+  int64_t sx, sy, sc;
+};
+
+// Result of steps a1-a3 (label classification, grouping/fusion, orientation,
+// gather directions).  The kernel computes
+//   C(m,n) = sum_k X(m,k) * Y(k,n)
+// with X(m,k) at x + xmn[m] + xk[k], Y(k,n) at y + yk[k] + ymn[n] and C(m,n)
+// at c + cm[m] + cn[n]; each offset vector is the column-major odometer over
+// its group's modes (first mode fastest), the same order for every operand
+// holding the group (conformal partitioning).
+struct Analysis {
+  int dtype = 0, compute = 0;
+  int64_t M = 0, N = 0, K = 0;
+  bool swapped = false;
+  bool x_kfast = true, y_kfast = true;
+  std::vector<Mode> I, J, P;
+  // address spans (element offsets relative to the base pointer) of the user
+  // tensors A, B, C: [lo, hi]; empty tensors have lo > hi.
+  int64_t a_lo = 0, a_hi = -1, b_lo = 0, b_hi = -1, c_lo = 0, c_hi = -1;
+  int64_t max_abs_x = 0, max_abs_y = 0, max_abs_c = 0;  // bounds on |offset sums|
+  int esize = 8;
+};
+
+int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tensor* B,
+            const famlies_tensor* C, Analysis* out, std::string* err);
+
+// Offset vector of length n_pad over `modes` using stride selector `which`
+// (0: X, 1: Y, 2: C); entries beyond `n` are 0 (a valid address whenever the
+// problem is non-empty).
+void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad,
+             std::vector<int64_t>& out);
+
+// Tile configuration of the plain kernels.
+struct TileCfg {
+  int bm = 128, bn = 128, bk = 16;
+  int split = 1;
+};
+
+void set_error(const std::string& msg);
+
+}  // namespace famlies

@@ -1,0 +1,290 @@
+// Host planner: label classification, mode grouping and fusion, orientation,
+// gather directions and block-scatter indexing vectors.
+//
+// The paper's block-scatter mapping (Approach, "Supporting tensor
+// computations") views a tensor as a matrix through per-row and per-column
+// offset vectors, so matrix code runs on the tensor with one extra level of
+// indirection and no tensor is ever transposed in memory (Approach,
+// "Variations on functionality": transposition by exchanging strides).  The
+// partitioning of the three index groups is conformal across the operands
+// that share them (Approach, "Flexible abstractions", footnote on C = AB).
+#include <algorithm>
+#include <cstdlib>
+#include <limits>
+
+#include "internal.hpp"
+
+namespace famlies {
+
+namespace {
+
+inline int64_t iabs(int64_t v) { return v < 0 ? -v : v; }
+
+bool check_tensor(const famlies_tensor* t, const char* name, std::string* err) {
+  if (!t) {
+    *err = std::string(name) + ": null descriptor";
+    return false;
+  }
+  if (t->rank < 0 || t->rank > FAMLIES_MAX_RANK) {
+    *err = std::string(name) + ": rank out of range [0, 8]";
+    return false;
+  }
+  if (t->rank > 0 && (!t->extents || !t->strides || !t->labels)) {
+    *err = std::string(name) + ": null extents/strides/labels";
+    return false;
+  }
+  for (int d = 0; d < t->rank; ++d) {
+    if (t->extents[d] < 0) {
+      *err = std::string(name) + ": negative extent";
+      return false;
+    }
+  }
+  return true;
+}
+
+int find(const famlies_tensor* t, int32_t label) {
+  for (int d = 0; d < t->rank; ++d)
+    if (t->labels[d] == label) return d;
+  return -1;
+}
+
+bool repeated(const famlies_tensor* t) {
+  for (int d = 0; d < t->rank; ++d)
+    for (int e = 0; e < d; ++e)
+      if (t->labels[d] == t->labels[e]) return true;
+  return false;
+}
+
+// [lo, hi] of element offsets; lo > hi when the tensor has no elements.
+void span(const famlies_tensor* t, int64_t* lo, int64_t* hi) {
+  int64_t l = 0, h = 0;
+  for (int d = 0; d < t->rank; ++d) {
+    if (t->extents[d] == 0) {
+      *lo = 0;
+      *hi = -1;
+      return;
+    }
+    int64_t r = (t->extents[d] - 1) * t->strides[d];
+    if (r < 0) l += r; else h += r;
+  }
+  *lo = l;
+  *hi = h;
+}
+
+// Sufficient condition for an injective layout: with modes of extent > 1
+// sorted by |stride|, every |stride| exceeds the largest offset reachable by
+// the smaller modes.
+bool injective(const famlies_tensor* t) {
+  std::vector<std::pair<int64_t, int64_t>> m;  // (|stride|, extent)
+  for (int d = 0; d < t->rank; ++d) {
+    if (t->extents[d] == 0) return true;  // no elements at all
+    if (t->extents[d] > 1) m.push_back({iabs(t->strides[d]), t->extents[d]});
+  }
+  std::sort(m.begin(), m.end());
+  int64_t reach = 0;
+  for (auto& s : m) {
+    if (s.first <= reach) return false;
+    reach += (s.second - 1) * s.first;
+  }
+  return true;
+}
+
+int64_t sel(const Mode& md, int which) { return which == 0 ? md.sx : which == 1 ? md.sy : md.sc; }
+
+// Fuse neighbours u, v (in group order) when, in every operand holding the
+// group, v's stride equals u's extent times u's stride: the pair then walks
+// memory exactly like one mode of extent e_u * e_v.
+std::vector<Mode> fuse(const std::vector<Mode>& in, int w1, int w2) {
+  std::vector<Mode> out;
+  for (const Mode& md : in) {
+    if (!out.empty()) {
+      Mode& u = out.back();
+      if (sel(md, w1) == u.ext * sel(u, w1) && sel(md, w2) == u.ext * sel(u, w2)) {
+        u.ext *= md.ext;
+        continue;
+      }
+    }
+    out.push_back(md);
+  }
+  return out;
+}
+
+int64_t min_abs(const std::vector<Mode>& g, int which) {
+  int64_t m = std::numeric_limits<int64_t>::max();
+  for (const Mode& md : g) m = std::min(m, iabs(sel(md, which)));
+  return m;
+}
+
+int64_t reach(const std::vector<Mode>& g, int which) {
+  int64_t r = 0;
+  for (const Mode& md : g) r += (md.ext - 1) * iabs(sel(md, which));
+  return r;
+}
+
+}  // namespace
+
+int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tensor* B,
+            const famlies_tensor* C, Analysis* out, std::string* err) {
+  if (dtype != FAMLIES_F64 && dtype != FAMLIES_F32) {
+    *err = "dtype must be FAMLIES_F64 or FAMLIES_F32";
+    return FAMLIES_ERR_INVALID_ARG;
+  }
+  if (compute != FAMLIES_NATIVE && compute != FAMLIES_BF16X3) {
+    *err = "compute must be FAMLIES_NATIVE or FAMLIES_BF16X3";
+    return FAMLIES_ERR_INVALID_ARG;
+  }
+  if (compute == FAMLIES_BF16X3 && dtype != FAMLIES_F32) {
+    *err = "bf16x3 compute needs FAMLIES_F32 data";
+    return FAMLIES_ERR_UNSUPPORTED;
+  }
+  if (!check_tensor(A, "A", err) || !check_tensor(B, "B", err) || !check_tensor(C, "C", err))
+    return FAMLIES_ERR_INVALID_ARG;
+  if (repeated(C)) {
+    *err = "a label is repeated within C";
+    return FAMLIES_ERR_LABEL;
+  }
+  if (repeated(A) || repeated(B)) {
+    *err = "a label repeated within A or B (diagonal) is not supported";
+    return FAMLIES_ERR_UNSUPPORTED;
+  }
+  Analysis an;
+  an.dtype = dtype;
+  an.compute = compute;
+  an.esize = dtype == FAMLIES_F64 ? 8 : 4;
+  std::vector<Mode> I, J, P;  // in user orientation: sx = A stride, sy = B stride
+  for (int d = 0; d < C->rank; ++d) {
+    int32_t l = C->labels[d];
+    int ia = find(A, l), ib = find(B, l);
+    if (ia >= 0 && ib >= 0) {
+      *err = "a label in A, B and C (batch mode) is not supported";
+      return FAMLIES_ERR_UNSUPPORTED;
+    }
+    if (ia < 0 && ib < 0) {
+      *err = "a label of C appears in neither A nor B";
+      return FAMLIES_ERR_LABEL;
+    }
+    if (ia >= 0) {
+      if (A->extents[ia] != C->extents[d]) {
+        *err = "extent mismatch between A and C";
+        return FAMLIES_ERR_SHAPE_MISMATCH;
+      }
+      I.push_back({l, C->extents[d], A->strides[ia], 0, C->strides[d]});
+    } else {
+      if (B->extents[ib] != C->extents[d]) {
+        *err = "extent mismatch between B and C";
+        return FAMLIES_ERR_SHAPE_MISMATCH;
+      }
+      J.push_back({l, C->extents[d], 0, B->strides[ib], C->strides[d]});
+    }
+  }
+  for (int d = 0; d < A->rank; ++d) {
+    int32_t l = A->labels[d];
+    if (find(C, l) >= 0) continue;
+    int ib = find(B, l);
+    if (ib < 0) {
+      *err = "a label only in A (trace) is not supported";
+      return FAMLIES_ERR_UNSUPPORTED;
+    }
+    if (B->extents[ib] != A->extents[d]) {
+      *err = "extent mismatch between A and B";
+      return FAMLIES_ERR_SHAPE_MISMATCH;
+    }
+    P.push_back({l, A->extents[d], A->strides[d], B->strides[ib], 0});
+  }
+  for (int d = 0; d < B->rank; ++d) {
+    int32_t l = B->labels[d];
+    if (find(C, l) < 0 && find(A, l) < 0) {
+      *err = "a label only in B (trace) is not supported";
+      return FAMLIES_ERR_UNSUPPORTED;
+    }
+  }
+  if (!injective(C)) {
+    *err = "C's layout maps two multi-indices to one address";
+    return FAMLIES_ERR_ALIAS;
+  }
+  span(A, &an.a_lo, &an.a_hi);
+  span(B, &an.b_lo, &an.b_hi);
+  span(C, &an.c_lo, &an.c_hi);
+
+  auto prod = [](const std::vector<Mode>& g) {
+    int64_t p = 1;
+    for (const Mode& m : g) p *= m.ext;
+    return p;
+  };
+  int64_t M = prod(I), N = prod(J), K = prod(P);
+
+  // Drop extent-1 modes (offset always 0).  Extent-0 modes stay so the
+  // products remain 0; such problems never reach a kernel.
+  auto drop1 = [](std::vector<Mode>& g) {
+    g.erase(std::remove_if(g.begin(), g.end(), [](const Mode& m) { return m.ext == 1; }), g.end());
+  };
+  drop1(I);
+  drop1(J);
+  drop1(P);
+
+  // Orientation: the kernel's N runs along the MFMA lane index, so C's
+  // smallest-stride mode should be a column mode.  If it is a row mode,
+  // compute C^T = B^T A^T: exchange the operands and the two groups.
+  int64_t ci = min_abs(I, 2), cj = min_abs(J, 2);
+  an.swapped = (!I.empty() && ci < cj);
+  if (an.swapped) {
+    std::swap(I, J);
+    std::swap(M, N);
+    for (Mode& m : I) std::swap(m.sx, m.sy);
+    for (Mode& m : J) std::swap(m.sx, m.sy);
+    for (Mode& m : P) std::swap(m.sx, m.sy);
+  }
+
+  // Order: rows and columns by C's stride; contracted modes by the operand
+  // with the smaller contracted stride (ties broken by the other operand).
+  auto by = [](int w1, int w2) {
+    return [w1, w2](const Mode& a, const Mode& b) {
+      int64_t x = iabs(sel(a, w1)), y = iabs(sel(b, w1));
+      if (x != y) return x < y;
+      return iabs(sel(a, w2)) < iabs(sel(b, w2));
+    };
+  };
+  std::stable_sort(I.begin(), I.end(), by(2, 0));
+  std::stable_sort(J.begin(), J.end(), by(2, 1));
+  if (min_abs(P, 0) <= min_abs(P, 1))
+    std::stable_sort(P.begin(), P.end(), by(0, 1));
+  else
+    std::stable_sort(P.begin(), P.end(), by(1, 0));
+  an.I = fuse(I, 0, 2);
+  an.J = fuse(J, 1, 2);
+  an.P = fuse(P, 0, 1);
+  an.M = M;
+  an.N = N;
+  an.K = K;
+
+  // Gather direction per operand: along the contracted modes when one of them
+  // has the operand's smallest stride (ties go to K, the LDS-contiguous way).
+  an.x_kfast = an.P.empty() ? false : (an.I.empty() || min_abs(an.P, 0) <= min_abs(an.I, 0));
+  an.y_kfast = an.P.empty() ? false : (an.J.empty() || min_abs(an.P, 1) <= min_abs(an.J, 1));
+  an.max_abs_x = reach(an.I, 0) + reach(an.P, 0);
+  an.max_abs_y = reach(an.J, 1) + reach(an.P, 1);
+  an.max_abs_c = reach(an.I, 2) + reach(an.J, 2);
+  *out = an;
+  return FAMLIES_OK;
+}
+
+void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad,
+             std::vector<int64_t>& out) {
+  out.assign(static_cast<size_t>(n_pad), 0);
+  std::vector<int64_t> digit(modes.size(), 0);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    out[static_cast<size_t>(i)] = off;
+    for (size_t d = 0; d < modes.size(); ++d) {
+      int64_t s = sel(modes[d], which);
+      if (++digit[d] < modes[d].ext) {
+        off += s;
+        break;
+      }
+      off -= (modes[d].ext - 1) * s;
+      digit[d] = 0;
+    }
+  }
+}
+
+}  // namespace famlies

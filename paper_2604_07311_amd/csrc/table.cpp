@@ -1,0 +1,93 @@
+// Tile table: text load/save and lookup by size class.
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <sstream>
+
+#include "runtime.hpp"
+
+namespace famlies {
+
+int TileTable::log2c(int64_t x) {
+  int l = 0;
+  while (((int64_t)1 << l) < x && l < 62) ++l;
+  return l;
+}
+
+bool TileTable::lookup_plain(const Analysis& an, TileCfg* out) const {
+  const int lm = log2c(an.M), ln = log2c(an.N), lk = log2c(an.K);
+  for (const Entry& e : entries)
+    if (e.kind == 0 && e.dtype == an.dtype && e.compute == an.compute && e.lm == lm && e.ln == ln &&
+        e.lk == lk) {
+      *out = e.cfg;
+      return true;
+    }
+  return false;
+}
+
+bool TileTable::lookup_batch(int dtype, int64_t m, int64_t n, int64_t k, TileCfg* out) const {
+  const int lm = log2c(m), ln = log2c(n), lk = log2c(k);
+  for (const Entry& e : entries)
+    if (e.kind == 1 && e.dtype == dtype && e.lm == lm && e.ln == ln && e.lk == lk) {
+      *out = e.cfg;
+      return true;
+    }
+  return false;
+}
+
+void TileTable::put(const Entry& e) {
+  for (Entry& x : entries)
+    if (x.kind == e.kind && x.dtype == e.dtype && x.compute == e.compute && x.lm == e.lm &&
+        x.ln == e.ln && x.lk == e.lk) {
+      x = e;
+      return;
+    }
+  entries.push_back(e);
+}
+
+// Format: '#' comments; one entry per line:
+//   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split>
+bool TileTable::load(const std::string& path, std::string* err) {
+  std::ifstream f(path);
+  if (!f) {
+    *err = "cannot open " + path;
+    return false;
+  }
+  std::string line;
+  int ln = 0;
+  std::vector<Entry> got;
+  while (std::getline(f, line)) {
+    ++ln;
+    if (line.empty() || line[0] == '#') continue;
+    std::istringstream is(line);
+    std::string kind;
+    Entry e;
+    if (!(is >> kind >> e.dtype >> e.compute >> e.lm >> e.ln >> e.lk >> e.cfg.bm >> e.cfg.bn >>
+          e.cfg.bk >> e.cfg.split) ||
+        (kind != "plain" && kind != "batch") || e.cfg.bm <= 0 || e.cfg.bn <= 0 || e.cfg.bk <= 0 ||
+        e.cfg.split <= 0) {
+      *err = path + ":" + std::to_string(ln) + ": malformed entry";
+      return false;
+    }
+    e.kind = kind == "plain" ? 0 : 1;
+    got.push_back(e);
+  }
+  for (const Entry& e : got) put(e);
+  return true;
+}
+
+bool TileTable::save(const std::string& path, std::string* err) const {
+  std::ofstream f(path);
+  if (!f) {
+    *err = "cannot write " + path;
+    return false;
+  }
+  f << "# famlies tile table: kind dtype compute log2M log2N log2K bm bn bk split\n";
+  for (const Entry& e : entries)
+    f << (e.kind == 0 ? "plain" : "batch") << ' ' << e.dtype << ' ' << e.compute << ' ' << e.lm << ' '
+      << e.ln << ' ' << e.lk << ' ' << e.cfg.bm << ' ' << e.cfg.bn << ' ' << e.cfg.bk << ' '
+      << e.cfg.split << '\n';
+  return (bool)f;
+}
+
+}  // namespace famlies

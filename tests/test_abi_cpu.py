@@ -1,0 +1,184 @@
+"""CPU tests of the C ABI library: it loads, exports every declared symbol,
+and its host planner (label classification, grouping, orientation,
+block-scatter indexing vectors, error codes) is right.  No compute call
+reaches a device here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "famlies.h")
+
+
+@pytest.fixture(scope="module")
+def fm():
+    import paper_2604_07311_amd as fm
+    if not os.path.exists(fm.LIB_PATH):
+        from paper_2604_07311_amd import build
+        build.build()
+    fm.load_library()
+    return fm
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(famlies_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(fm):
+    lib = fm.load_library()
+    names = declared_symbols()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(fm.EXPORTS)
+
+
+def test_version_and_last_error(fm):
+    assert "gfx950" in fm.famlies_version()
+    assert isinstance(fm.famlies_last_error(), str)
+
+
+def desc(fm, lay, labels):
+    return fm.make_desc(lay.extents, lay.strides, labels)
+
+
+def analyze(fm, p, dtype=None, compute=0, offsets=False):
+    dtype = dtype or fm.FAMLIES_F64
+    return fm.famlies_analyze(dtype, compute, desc(fm, p.a, p.la), desc(fm, p.b, p.lb),
+                              desc(fm, p.c, p.lc), want_offsets=offsets)
+
+
+def test_plain16_classification(fm):
+    p = synth.plain16(with_data=False)
+    info, _ = analyze(fm, p)
+    assert (info["m"], info["n"], info["k"]) == (256, 256, 256)
+    # C[a,b,i,j]: a has C stride 1 and is an I mode -> swapped so it lies in N
+    assert info["swapped"] == 1
+    # nothing fuses in A[a,e,i,f] or B[e,b,f,j]: two modes per group
+    assert (info["n_i"], info["n_j"], info["n_p"]) == (2, 2, 2)
+    assert info["flops"] == 2.0 * 256 ** 3
+
+
+def test_ladder_grouping(fm):
+    p = synth.ladder(128, 32, with_data=False)
+    info, _ = analyze(fm, p)
+    # kernel view after the swap: X = T (rows ij, fused), Y = W (columns ab)
+    assert info["swapped"] == 1
+    assert (info["m"], info["n"], info["k"]) == (1024, 16384, 16384)
+    assert info["n_i"] == 1          # i,j fuse in T and C
+    assert info["n_j"] == 2          # a,b do not fuse in W (stored e,a,f,b)
+    assert info["n_p"] == 2          # e,f do not fuse in W
+    assert info["x_kfast"] == 1 and info["y_kfast"] == 1  # T and W both have stride 1 on e
+
+
+def test_ring_grouping(fm):
+    p = synth.ring(48, 192, with_data=False)
+    info, _ = analyze(fm, p, dtype=fm.FAMLIES_F32, compute=fm.FAMLIES_BF16X3)
+    assert (info["m"], info["n"], info["k"]) == (9216, 9216, 9216)
+
+
+def _check_offsets(fm, p):
+    info, off = analyze(fm, p, offsets=True)
+    # Every (m,k) / (k,n) / (m,n) maps to a distinct element of the tensor and
+    # the union is exactly the tensor's element set.
+    swapped = info["swapped"]
+    X, Y = (p.b, p.a) if swapped else (p.a, p.b)
+    def elems(r, c):
+        return (r[:, None] + c[None, :]).ravel()
+    from tests.famlies_testutil import used_offsets
+    for lay, r, c in ((X, off["xrow"], off["xk"]), (Y, off["yk"], off["ycol"]),
+                      (p.c, off["crow"], off["ccol"])):
+        got = np.sort(elems(r, c) + lay.base)
+        want = np.sort(used_offsets(lay))
+        if all(s != 0 for s in lay.strides):
+            np.testing.assert_array_equal(got, want)
+        else:
+            assert got.size == want.size
+    return info, off
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_block_scatter_vectors_cover_tensors(fm, seed):
+    rng = np.random.default_rng(500 + seed)
+    p = synth.random_problem(rng, lo=1, hi=6, pad_hi=2)
+    _check_offsets(fm, p)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_block_scatter_gemm_equals_oracle(fm, oracle_lib, seed):
+    """Running the kernel view's GEMM with numpy through the planner's
+    indexing vectors reproduces the oracle (integer data: exact)."""
+    import oracle
+    rng = np.random.default_rng(600 + seed)
+    p = synth.random_problem(rng, lo=1, hi=6, pad_hi=2)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    info, off = analyze(fm, p, offsets=True)
+    Xb, Xl, Yb, Yl = (p.bbuf, p.b, p.abuf, p.a) if info["swapped"] else (p.abuf, p.a, p.bbuf, p.b)
+    Xm = Xb[Xl.base + off["xrow"][:, None] + off["xk"][None, :]]
+    Ym = Yb[Yl.base + off["yk"][:, None] + off["ycol"][None, :]]
+    out = p.cbuf.copy()
+    cidx = p.c.base + off["crow"][:, None] + off["ccol"][None, :]
+    out[cidx] = p.alpha * (Xm @ Ym) + p.beta * p.cbuf[cidx]
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    np.testing.assert_array_equal(out, want)
+
+
+def test_negative_and_zero_strides_offsets(fm):
+    a = synth.layout([3, 4], negate=[True, False])
+    b = synth.layout([4, 5], zero=[False, True])
+    c = synth.layout([3, 5], order=[1, 0])
+    p = synth.Problem("t", "ik", "kj", "ij", a, b, c, 1.0, 0.0)
+    _check_offsets(fm, p)
+
+
+def _err(fm, la, lb, lc, ea, eb, ec, sa=None, sb=None, sc=None, dtype=None, compute=0):
+    sa = sa or [1] * len(ea)
+    sb = sb or [1] * len(eb)
+    sc = sc or list(np.cumprod([1] + list(ec[:-1]))) if ec else []
+    with pytest.raises(fm.FamliesError) as e:
+        fm.famlies_analyze(dtype or fm.FAMLIES_F64, compute, fm.make_desc(ea, sa, la),
+                           fm.make_desc(eb, sb, lb), fm.make_desc(ec, sc, lc))
+    return e.value.code
+
+
+def test_error_codes(fm):
+    assert _err(fm, "ik", "kj", "ij", [2, 3], [4, 5], [2, 5]) == fm.FAMLIES_ERR_SHAPE_MISMATCH
+    assert _err(fm, "ik", "kj", "iz", [2, 3], [3, 5], [2, 5]) == fm.FAMLIES_ERR_LABEL
+    assert _err(fm, "ik", "kj", "ii", [2, 3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_LABEL
+    assert _err(fm, "bik", "bkj", "bij", [2, 2, 3], [2, 3, 2], [2, 2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
+    assert _err(fm, "ikt", "kj", "ij", [2, 3, 2], [3, 2], [2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
+    assert _err(fm, "iik", "kj", "ij", [2, 2, 3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
+    assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2], sc=[1, 1]) == fm.FAMLIES_ERR_ALIAS
+    assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2], dtype=7) == fm.FAMLIES_ERR_INVALID_ARG
+    assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2],
+                compute=fm.FAMLIES_BF16X3) == fm.FAMLIES_ERR_UNSUPPORTED
+    assert _err(fm, "ik", "kj", "ij", [2, -3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_INVALID_ARG
+    big = list("abcdefghi")
+    assert _err(fm, "".join(big), "j", "j", [1] * 9, [2], [2]) == fm.FAMLIES_ERR_INVALID_ARG
+
+
+def test_degenerate_shapes(fm):
+    # scalar output (dot product), empty K, empty C
+    info, _ = fm.famlies_analyze(fm.FAMLIES_F32, 0, fm.make_desc([5], [1], "k"),
+                                 fm.make_desc([5], [2], "k"), fm.make_desc([], [], ""))
+    assert (info["m"], info["n"], info["k"]) == (1, 1, 5)
+    info, _ = fm.famlies_analyze(fm.FAMLIES_F32, 0, fm.make_desc([3, 0], [1, 3], "ik"),
+                                 fm.make_desc([0, 2], [1, 1], "kj"), fm.make_desc([3, 2], [1, 3], "ij"))
+    assert info["k"] == 0
+    info, _ = fm.famlies_analyze(fm.FAMLIES_F32, 0, fm.make_desc([0, 4], [1, 1], "ik"),
+                                 fm.make_desc([4, 2], [1, 4], "kj"), fm.make_desc([0, 2], [1, 1], "ij"))
+    assert info["m"] == 0
+
+
+def test_no_gpu_means_loud_failure(fm):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(fm.FamliesError):
+        fm.famlies_create(0)
