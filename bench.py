@@ -1,12 +1,19 @@
 """Benchmark: strided tensor contraction on one MI355X.
 
-Default workload: the coupled-cluster particle-particle ladder
-C[a,b,i,j] += sum_{e,f} W[a,b,e,f] T[e,f,i,j] at v=128, o=32 (M=1024 x
-N=16384 x K=16384 in the kernel view, 5.50e11 flop), W stored in mode order
-(e,a,f,b), FP64 (headline) and FP32, synthetic U[-1,1] data.
+Workloads (synthetic, seeded; see the design doc for the recipes):
+  ladder    (default) C[a,b,i,j] += sum_{e,f} W[a,b,e,f] T[e,f,i,j], v=128, o=32,
+            W stored in mode order (e,a,f,b); FP64 headline, FP32 secondary.
+  ladder3   the same ladder at v=192, o=48 with outliers: FP32 vs bf16x3.
+  ring      C[a,i,b,j] = sum_{k,c} X[a,k,i,c] Y[c,b,k,j], o=48, v=192: FP32 vs bf16x3.
+  batched   20,000 random 4-index FP32 contractions, one persistent launch
+            replayed from a HIP graph.
+  autograd  forward + backward (dA, dB) of C[a,b,i,j] = sum A[a,e,i,f] B[e,b,f,j],
+            o=24, v=96, FP32.
+  plain16   C[a,b,i,j] = sum A[a,e,i,f] B[e,b,f,j], all extents 16, FP64: latency,
+            single call and 1,000 calls replayed from a graph.
 
-A step is one contraction call (famlies_execute on a cached plan: gather ->
-MFMA -> scatter-update) with inputs resident in HBM.  Prints one JSON line.
+A step is one pass of the workload's contraction(s) with inputs resident in
+HBM.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,99 +29,130 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
-HBM_PEAK = 8.0e12
+METRIC = "contraction GFLOP/s & % MFMA peak (FP64/FP32/bf16x3) at stated err vs FP64"
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def make_ladder(v, o, dtype, seed=2):
-    import synth
-    npdt = np.float64 if dtype == "f64" else np.float32
-    p = synth.ladder(v, o, seed=seed, dtype=npdt)
-    return p
+def cores_used():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
-def run_one(p, dtype, compute, steps, warmup, sample_check=2048):
-    import torch
-    import paper_2604_07311_amd as fm
-    dev = torch.device("cuda:0")
-    code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-    comp = fm.FAMLIES_BF16X3 if compute == "bf16x3" else fm.FAMLIES_NATIVE
-    h = fm.handle(0)
-    t0 = time.time()
-    plan = fm.famlies_plan_contract(h, code, comp, fm.make_desc(p.a.extents, p.a.strides, p.la),
-                                    fm.make_desc(p.b.extents, p.b.strides, p.lb),
-                                    fm.make_desc(p.c.extents, p.c.strides, p.lc))
-    plan_s = time.time() - t0
-    info = fm.famlies_plan_get_info(plan)
-    a = torch.from_numpy(p.abuf).to(dev)
-    b = torch.from_numpy(p.bbuf).to(dev)
-    c0 = torch.from_numpy(p.cbuf).to(dev)
-    c = c0.clone()
-    stream = torch.cuda.current_stream(dev)
-    sh = stream.cuda_stream
-    es = a.element_size()
-
-    def step():
-        fm.famlies_execute(plan, p.alpha, a.data_ptr() + es * p.a.base, b.data_ptr() + es * p.b.base,
-                           p.beta, c.data_ptr() + es * p.c.base, sh)
-
-    # correctness of the timed configuration: one call from C0, sampled
-    # entries checked against the oracle (CPU, FP64)
-    step()
-    torch.cuda.synchronize()
-    got = c.cpu().numpy().astype(np.float64)
-    check = sample_parity(p, got, dtype, compute, sample_check)
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for e0, e1 in evs:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
-    per = [e0.elapsed_time(e1) for e0, e1 in evs]
-    fm.famlies_plan_destroy(plan)
-    del a, b, c, c0
-    torch.cuda.empty_cache()
-    return {"info": info, "ms_per_step": total_ms / steps, "launch_ms_avg": float(np.mean(per)),
-            "launch_ms_min": float(np.min(per)), "plan_s": plan_s, "check": check}
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def sample_parity(p, got, dtype, compute, n):
-    """Oracle on n random C entries of the timed configuration."""
+class Timer:
+    """HIP events on the stream the kernels are launched on."""
+
+    def __init__(self, stream):
+        import torch
+        self.torch = torch
+        self.stream = stream
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(self.stream)
+        for e0, e1 in evs:
+            e0.record(self.stream)
+            fn()
+            e1.record(self.stream)
+        end.record(self.stream)
+        torch.cuda.synchronize()
+        per = [e0.elapsed_time(e1) for e0, e1 in evs]
+        return start.elapsed_time(end) / steps, float(np.mean(per)), float(np.min(per))
+
+
+# ------------------------------------------------------------ single problems
+class Single:
+    """One labelled contraction planned once and executed through the C ABI."""
+
+    def __init__(self, p, dtype, compute="native"):
+        import torch
+        import paper_2604_07311_amd as fm
+        self.p, self.dtype, self.compute = p, dtype, compute
+        self.fm, self.torch = fm, torch
+        code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
+        comp = fm.FAMLIES_BF16X3 if compute == "bf16x3" else fm.FAMLIES_NATIVE
+        t0 = time.perf_counter()
+        self.plan = fm.famlies_plan_contract(fm.handle(0), code, comp,
+                                             fm.make_desc(p.a.extents, p.a.strides, p.la),
+                                             fm.make_desc(p.b.extents, p.b.strides, p.lb),
+                                             fm.make_desc(p.c.extents, p.c.strides, p.lc))
+        self.plan_s = time.perf_counter() - t0
+        self.info = fm.famlies_plan_get_info(self.plan)
+        npdt = np.float64 if dtype == "f64" else np.float32
+        dev = torch.device("cuda:0")
+        self.a = torch.from_numpy(np.ascontiguousarray(p.abuf, dtype=npdt)).to(dev)
+        self.b = torch.from_numpy(np.ascontiguousarray(p.bbuf, dtype=npdt)).to(dev)
+        self.c0 = torch.from_numpy(np.ascontiguousarray(p.cbuf, dtype=npdt)).to(dev)
+        self.c = self.c0.clone()
+        self.stream = torch.cuda.current_stream(dev)
+        es = self.a.element_size()
+        self.ptrs = (self.a.data_ptr() + es * p.a.base, self.b.data_ptr() + es * p.b.base,
+                     self.c.data_ptr() + es * p.c.base)
+
+    def step(self):
+        self.fm.famlies_execute(self.plan, self.p.alpha, self.ptrs[0], self.ptrs[1], self.p.beta,
+                                self.ptrs[2], self.stream.cuda_stream)
+
+    def result_once(self):
+        """C after one call from C0 (float64 numpy storage)."""
+        self.c.copy_(self.c0)
+        self.step()
+        self.torch.cuda.synchronize()
+        return self.c.cpu().numpy().astype(np.float64)
+
+    def close(self):
+        self.fm.famlies_plan_destroy(self.plan)
+        del self.a, self.b, self.c, self.c0
+        self.torch.cuda.empty_cache()
+
+
+def rounded(buf, dtype):
+    return buf.astype(np.float32).astype(np.float64) if dtype != "f64" else buf.astype(np.float64)
+
+
+def sample_check(p, got, dtype, n=2048, split=False, seed=1234):
+    """Oracle (FP64) on n random C entries; returns error statistics."""
     import oracle
-    rng = np.random.default_rng(1234)
+    rng = np.random.default_rng(seed)
     idx = np.stack([rng.integers(0, e, size=n) for e in p.c.extents], axis=1)
-    a = (p.abuf.astype(np.float64), p.a.base, p.a.extents, p.a.strides)
-    b = (p.bbuf.astype(np.float64), p.b.base, p.b.extents, p.b.strides)
-    c = (p.cbuf.astype(np.float64), p.c.base, p.c.extents, p.c.strides)
+    a = (rounded(p.abuf, dtype), p.a.base, p.a.extents, p.a.strides)
+    b = (rounded(p.bbuf, dtype), p.b.base, p.b.extents, p.b.strides)
+    c = (rounded(p.cbuf, dtype), p.c.base, p.c.extents, p.c.strides)
     want, d = oracle.contract_entries(p.alpha, a, p.la, b, p.lb, p.beta, c, p.lc, idx,
                                       want_cond=True)
-    offs = p.c.base + idx @ np.array(p.c.strides)
+    offs = p.c.base + idx @ np.array(p.c.strides, dtype=np.int64)
     g = got[offs]
-    rel = float(np.linalg.norm(g - want) / np.linalg.norm(want))
-    comp = float(np.max(np.abs(g - want) / np.maximum(d, 1e-300)))
-    return {"samples": int(n), "normwise_rel_err": rel, "max_err_over_D": comp}
+    return {"samples": int(n), "normwise_rel_err": float(np.linalg.norm(g - want) / np.linalg.norm(want)),
+            "max_abs_err_over_D": float(np.max(np.abs(g - want) / np.maximum(d, 1e-300)))}
 
 
 def cpu_baseline(p, target_s=12.0):
-    """The oracle, untuned, on a bounded sample of the same workload: a set of
-    randomly chosen C entries, each a full K-term dot product in FP64."""
+    """The oracle as it stands, on a bounded sample of the same workload:
+    randomly chosen C entries, each a full K-term FP64 dot product, on all the
+    host cores this process may use."""
     import oracle
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
+    cores = cores_used()
     K = 1
     for ch, e in zip(p.la, p.a.extents):
         if ch in p.lb:
@@ -130,24 +168,257 @@ def cpu_baseline(p, target_s=12.0):
         oracle.contract_entries(p.alpha, a, p.la, b, p.lb, p.beta, c, p.lc, idx, nthreads=cores)
         return time.perf_counter() - t0
 
-    n0 = 256 * cores
+    n0 = 64 * cores
     t0 = timed(n0)
     n = int(max(n0, min(n0 * target_s / max(t0, 1e-3), 5e7)))
     t = timed(n)
-    flops = 2.0 * K * n
-    return {"value": flops / t / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random C entries of the ladder (each a %d-term FP64 dot product), "
-                      "%.1f s" % (n, K, t)}
+    return {"value": round(2.0 * K * n / t / 1e9, 3), "unit": "GFLOP/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "%d random C entries of %s, each a %d-term FP64 dot product (%.1f s)"
+                      % (n, p.name, K, t)}
 
 
-def cpu_model():
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
+def roofline(flops, launch_ms, peak, bound="mfma"):
+    achieved = flops / (launch_ms * 1e-3) / 1e12
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1),
+            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4), "traffic": None}
+
+
+def base_record(args, value, ms, dtype, config, unit="GFLOP/s"):
+    return {"metric": METRIC, "value": round(value, 2), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def wl_ladder(args):
+    import synth
+    res = {}
+    probs = {}
+    for dtype in (["f64", "f32"] if args.only is None else [args.only]):
+        log("ladder v=%d o=%d %s: generating" % (args.v, args.o, dtype))
+        p = synth.ladder(args.v, args.o, seed=2,
+                         dtype=np.float64 if dtype == "f64" else np.float32)
+        probs[dtype] = p
+        s = Single(p, dtype)
+        check = sample_check(p, s.result_once(), dtype)
+        ms, launch, lmin = Timer(s.stream).run(s.step, args.steps, args.warmup)
+        res[dtype] = {"ms": ms, "launch": launch, "info": s.info, "check": check, "plan_s": s.plan_s}
+        log("%s: %.3f ms/step (%.1f GFLOP/s) check %s" % (dtype, ms, s.info["flops"] / ms / 1e6, check))
+        s.close()
+    head = "f64" if "f64" in res else list(res)[0]
+    r = res[head]
+    flops = r["info"]["flops"]
+    out = base_record(args, flops / (r["ms"] * 1e-3) / 1e9, r["ms"], head,
+                      {"workload": "ccsd_ladder_v%d_o%d" % (args.v, args.o),
+                       "contraction": "C[a,b,i,j] += sum_ef W[a,b,e,f] T[e,f,i,j]; W stored (e,a,f,b)",
+                       "m": r["info"]["m"], "n": r["info"]["n"], "k": r["info"]["k"],
+                       "tile": [r["info"]["tile_m"], r["info"]["tile_n"], r["info"]["tile_k"]],
+                       "split_k": r["info"]["split_k"]})
+    out["pct_mfma_peak"] = round(100 * flops / (r["ms"] * 1e-3) / PEAK[head], 2)
+    out["error_vs_fp64"] = r["check"]
+    out["roofline"] = roofline(flops, r["launch"], PEAK[head])
+    for dt, rr in res.items():
+        if dt == head:
+            continue
+        v = rr["info"]["flops"] / (rr["ms"] * 1e-3)
+        out.setdefault("secondary", {})[dt] = {
+            "value": round(v / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(rr["ms"], 4),
+            "pct_mfma_peak": round(100 * v / PEAK[dt], 2), "error_vs_fp64": rr["check"],
+            "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt])}
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(probs[head])
+    return out
+
+
+def _fp32_vs_bf16x3(args, p, name):
+    res = {}
+    for comp in ("native", "bf16x3"):
+        s = Single(p, "f32", comp)
+        check = sample_check(p, s.result_once(), "f32", n=1024)
+        ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
+        res[comp] = {"ms": ms, "launch": launch, "info": s.info, "check": check}
+        log("%s %s: %.3f ms (%.1f GFLOP/s) check %s" % (name, comp, ms, s.info["flops"] / ms / 1e6, check))
+        s.close()
+    r3, r32 = res["bf16x3"], res["native"]
+    flops = r3["info"]["flops"]
+    out = base_record(args, flops / (r3["ms"] * 1e-3) / 1e9, r3["ms"], "bf16x3",
+                      {"workload": name, "m": r3["info"]["m"], "n": r3["info"]["n"],
+                       "k": r3["info"]["k"]})
+    out["gflops_fp32_equivalent"] = round(flops / (r3["ms"] * 1e-3) / 1e9, 2)
+    out["pct_fp32_mfma_peak"] = round(100 * flops / (r3["ms"] * 1e-3) / PEAK["f32"], 2)
+    out["issued_bf16_tflops"] = round(3 * flops / (r3["ms"] * 1e-3) / 1e12, 2)
+    out["error_vs_fp64"] = r3["check"]
+    out["fp32"] = {"ms_per_step": round(r32["ms"], 4),
+                   "value": round(flops / (r32["ms"] * 1e-3) / 1e9, 2),
+                   "pct_mfma_peak": round(100 * flops / (r32["ms"] * 1e-3) / PEAK["f32"], 2),
+                   "error_vs_fp64": r32["check"]}
+    out["speedup_vs_fp32"] = round(r32["ms"] / r3["ms"], 3)
+    out["roofline"] = roofline(3 * flops, r3["launch"], PEAK["bf16"])
+    return out
+
+
+def wl_ladder3(args):
+    import synth
+    log("ladder v=192 o=48 with outliers (FP32): generating")
+    p = synth.ladder(192, 48, seed=3, dist="outliers", dtype=np.float32)
+    return _fp32_vs_bf16x3(args, p, "ccsd_ladder_v192_o48_outliers")
+
+
+def wl_ring(args):
+    import synth
+    log("ring o=48 v=192 with outliers (FP32): generating")
+    p = synth.ring(48, 192, seed=4, dist="outliers", dtype=np.float32)
+    return _fp32_vs_bf16x3(args, p, "ccsd_ring_o48_v192_outliers")
+
+
+def wl_plain16(args):
+    import torch
+    import synth
+    p = synth.plain16(seed=1)
+    s = Single(p, "f64")
+    check = sample_check(p, s.result_once(), "f64", n=4096)
+    ms, launch, lmin = Timer(s.stream).run(s.step, args.steps, args.warmup)
+    # 1,000 calls replayed from one graph
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        s.stream = cs
+        with torch.cuda.graph(g, stream=cs):
+            for _ in range(1000):
+                s.step()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    per_call_graph = e0.elapsed_time(e1) / 1000
+    flops = s.info["flops"]
+    out = base_record(args, flops / (ms * 1e-3) / 1e9, ms, "f64",
+                      {"workload": "plain16", "m": 256, "n": 256, "k": 256,
+                       "tile": [s.info["tile_m"], s.info["tile_n"], s.info["tile_k"]],
+                       "split_k": s.info["split_k"]})
+    out["latency_us_single_call"] = round(ms * 1e3, 2)
+    out["latency_us_per_call_in_graph"] = round(per_call_graph * 1e3, 2)
+    out["gflops_in_graph"] = round(flops / (per_call_graph * 1e-3) / 1e9, 2)
+    out["error_vs_fp64"] = check
+    out["roofline"] = roofline(flops, launch, PEAK["f64"])
+    del g
+    s.close()
+    return out
+
+
+def wl_autograd(args):
+    import torch
+    import paper_2604_07311_amd as fm
+    import synth
+    o, v = 24, 96
+    p = synth.autograd_case(o, v, seed=6)
+    A = torch.from_numpy(p.abuf.astype(np.float32)).cuda().as_strided((v, v, o, v), p.a.strides)
+    B = torch.from_numpy(p.bbuf.astype(np.float32)).cuda().as_strided((v, v, v, o), p.b.strides)
+    G = torch.from_numpy(p.meta["G"].astype(np.float32)).cuda().as_strided((v, v, o, o), p.c.strides)
+    A.requires_grad_()
+    B.requires_grad_()
+
+    def step():
+        A.grad = None
+        B.grad = None
+        C = fm.contract_ad(1.0, A, "aeif", B, "ebfj", 0.0, None, "abij")
+        C.backward(G)
+
+    step()
+    torch.cuda.synchronize()
+    ms, launch, _ = Timer(torch.cuda.current_stream()).run(step, args.steps, args.warmup)
+    # forward: M = a*i = v*o, N = b*j = v*o, K = e*f = v*v; dA and dB have the same volume
+    flops = 3 * 2.0 * (v * o) * (v * o) * (v * v)
+    out = base_record(args, flops / (ms * 1e-3) / 1e9, ms, "f32",
+                      {"workload": "autograd_o24_v96", "contractions_per_step": 3,
+                       "m": v * o, "n": v * o, "k": v * v})
+    out["pct_mfma_peak"] = round(100 * flops / (ms * 1e-3) / PEAK["f32"], 2)
+    out["roofline"] = roofline(flops, launch, PEAK["f32"])
+    return out
+
+
+def wl_batched(args):
+    import torch
+    import paper_2604_07311_amd as fm
+    import oracle
+    import synth
+    n = args.batch
+    log("batched: planning %d problems" % n)
+    probs = synth.batched(n, seed=5)
+    # read-only operands alias into one shared pool; outputs are disjoint
+    pool_n = max(max(p.a.size for p in probs), max(p.b.size for p in probs)) * 8
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    pool = torch.rand(pool_n, generator=gen, device="cuda", dtype=torch.float32) * 2 - 1
+    rng = np.random.default_rng(55)
+    aoff = [int(rng.integers(0, pool_n - p.a.size + 1)) for p in probs]
+    boff = [int(rng.integers(0, pool_n - p.b.size + 1)) for p in probs]
+    coff = np.concatenate([[0], np.cumsum([p.c.size for p in probs])]).astype(np.int64)
+    C0 = torch.rand(int(coff[-1]), generator=gen, device="cuda", dtype=torch.float32) * 2 - 1
+    C = C0.clone()
+    pa = torch.tensor([pool.data_ptr() + 4 * (aoff[i] + p.a.base) for i, p in enumerate(probs)],
+                      dtype=torch.int64, device="cuda")
+    pb = torch.tensor([pool.data_ptr() + 4 * (boff[i] + p.b.base) for i, p in enumerate(probs)],
+                      dtype=torch.int64, device="cuda")
+    pc = torch.tensor([C.data_ptr() + 4 * (int(coff[i]) + p.c.base) for i, p in enumerate(probs)],
+                      dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    plan = fm.famlies_batch_plan(fm.handle(0), fm.FAMLIES_F32,
+                                 [fm.make_desc(p.a.extents, p.a.strides, p.la) for p in probs],
+                                 [fm.make_desc(p.b.extents, p.b.strides, p.lb) for p in probs],
+                                 [fm.make_desc(p.c.extents, p.c.strides, p.lc) for p in probs])
+    plan_s = time.perf_counter() - t0
+    flops = sum(2.0 * np.prod(synth.sizes(p)) for p in probs)
+    stream = torch.cuda.Stream()
+
+    def launch(s):
+        fm.famlies_batch_execute(plan, 1.0, 0.5, pa.data_ptr(), pb.data_ptr(), pc.data_ptr(),
+                                 s.cuda_stream)
+
+    # eager run from C0, then check sampled problems fully against the oracle
+    with torch.cuda.stream(stream):
+        launch(stream)
+    torch.cuda.synchronize()
+    pool_h = pool.cpu().numpy().astype(np.float64)
+    C_h = C.cpu().numpy().astype(np.float64)
+    C0_h = C0.cpu().numpy().astype(np.float64)
+    worst = 0.0
+    checked = 0
+    for i in rng.choice(n, size=min(n, 24), replace=False):
+        p = probs[i]
+        a = (pool_h[aoff[i]:aoff[i] + p.a.size], p.a.base, p.a.extents, p.a.strides)
+        b = (pool_h[boff[i]:boff[i] + p.b.size], p.b.base, p.b.extents, p.b.strides)
+        c = (C0_h[coff[i]:coff[i + 1]], p.c.base, p.c.extents, p.c.strides)
+        want, d = oracle.contract(1.0, a, p.la, b, p.lb, 0.5, c, p.lc, want_cond=True)
+        got = C_h[coff[i]:coff[i + 1]]
+        worst = max(worst, float(np.max(np.abs(got - want) / np.maximum(d, 1e-300))))
+        checked += 1
+    # graph capture of the single launch, replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            launch(stream)
+    torch.cuda.synchronize()
+    ms, launch_ms, _ = Timer(torch.cuda.current_stream()).run(g.replay, args.steps, args.warmup)
+    out = base_record(args, flops / (ms * 1e-3) / 1e9, ms, "f32",
+                      {"workload": "batched_%d_random_4index" % n, "problems": n,
+                       "dims": "U{4..48}", "launch": "one persistent kernel, graph replay"})
+    out["pct_mfma_peak"] = round(100 * flops / (ms * 1e-3) / PEAK["f32"], 2)
+    out["plan_s"] = round(plan_s, 3)
+    out["error_vs_fp64"] = {"problems_checked_fully": checked, "max_abs_err_over_D": worst}
+    out["roofline"] = roofline(flops, launch_ms, PEAK["f32"])
+    del g
+    fm.famlies_plan_destroy(plan)
+    return out
+
+
+WORKLOADS = {"ladder": wl_ladder, "ladder3": wl_ladder3, "ring": wl_ring, "plain16": wl_plain16,
+             "autograd": wl_autograd, "batched": wl_batched}
 
 
 def main():
@@ -155,72 +426,33 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ladder")
     ap.add_argument("--v", type=int, default=128)
     ap.add_argument("--o", type=int, default=32)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain device copy of this many bytes (a known-size "
+                         "reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design for sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (how the "
+              "contraction would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    log("device %s" % torch.cuda.get_device_name(0))
-    results = {}
-    problems = {}
-    for dtype in (["f64", "f32"] if args.only is None else [args.only]):
-        log("generating ladder v=%d o=%d %s" % (args.v, args.o, dtype))
-        p = make_ladder(args.v, args.o, dtype)
-        problems[dtype] = p
-        log("running %s: %d warmup + %d timed steps" % (dtype, args.warmup, args.steps))
-        results[dtype] = run_one(p, dtype, "native", args.steps, args.warmup)
-        r = results[dtype]
-        log("%s: %.3f ms/step, %.1f GFLOP/s, check %s" % (
-            dtype, r["ms_per_step"], r["info"]["flops"] / r["ms_per_step"] / 1e6, r["check"]))
-    head = "f64" if "f64" in results else list(results)[0]
-    r = results[head]
-    flops = r["info"]["flops"]
-    value = flops / (r["ms_per_step"] * 1e-3) / 1e9
-    achieved = flops / (r["launch_ms_avg"] * 1e-3) / 1e12
-    out = {
-        "metric": "contraction GFLOP/s & % MFMA peak (FP64/FP32/bf16x3) at stated err vs FP64",
-        "value": round(value, 2),
-        "unit": "GFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r["ms_per_step"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": head,
-        "data": "synthetic",
-        "config": {"workload": "ccsd_ladder_v%d_o%d" % (args.v, args.o),
-                   "contraction": "C[a,b,i,j] += sum_ef W[a,b,e,f] T[e,f,i,j], W stored (e,a,f,b)",
-                   "m": r["info"]["m"], "n": r["info"]["n"], "k": r["info"]["k"],
-                   "tile": [r["info"]["tile_m"], r["info"]["tile_n"], r["info"]["tile_k"]],
-                   "split_k": r["info"]["split_k"], "parallelism": "single GPU"},
-        "pct_mfma_peak": round(100.0 * value * 1e9 / PEAK[head], 2),
-        "error_vs_fp64": r["check"],
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[head] / 1e12,
-                     "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK[head], 4),
-                     "traffic": None},
-    }
-    if len(results) > 1:
-        out["secondary"] = {}
-        for dt, rr in results.items():
-            if dt == head:
-                continue
-            v = rr["info"]["flops"] / (rr["ms_per_step"] * 1e-3) / 1e9
-            out["secondary"][dt] = {"value": round(v, 2), "unit": "GFLOP/s",
-                                    "ms_per_step": round(rr["ms_per_step"], 4),
-                                    "pct_mfma_peak": round(100.0 * v * 1e9 / PEAK[dt], 2),
-                                    "error_vs_fp64": rr["check"]}
-    if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(problems[head])
-        out["cpu_baseline"]["cpu_model"] = cpu_model()
+    log("device %s, workload %s" % (torch.cuda.get_device_name(0), args.workload))
+    if args.copy_bytes > 0:
+        n = args.copy_bytes // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("reference copy: %d bytes read, %d bytes written" % (4 * n, 4 * n))
+        del src, dst
+    out = WORKLOADS[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

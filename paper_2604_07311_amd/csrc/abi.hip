@@ -185,6 +185,61 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   return a;
 }
 
+famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int compute,
+                         const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                         const TileCfg* force) {
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
+  *out = nullptr;
+  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
+  Analysis an;
+  std::string err;
+  int st = analyze(dtype, compute, A, B, C, &an, &err);
+  if (st != FAMLIES_OK) return fail(st, err);
+  const int64_t lim = ((int64_t)1 << 31) - 1024;
+  if (an.M > lim || an.N > lim || an.K > lim)
+    return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
+  auto* p = new (std::nothrow) famlies_plan_s();
+  if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  p->h = h;
+  p->an = an;
+  p->index_bits = index_bits_for(an);
+  p->cfg = force ? *force : choose_tiles(h, an);
+  if (compute == FAMLIES_BF16X3) {
+    p->cfg.bk = 32;
+    if (!bf16x3_tile_supported(p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
+  } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
+    p->cfg.bm = p->cfg.bn = 128;
+    p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
+  }
+  finalize_split(&p->cfg, an.K, &p->kchunk);
+  const bool empty = an.M == 0 || an.N == 0;
+  if (!empty) {
+    const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
+    const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
+    const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
+    st = p->index_bits == 32 ? upload<int32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
+    if (st != FAMLIES_OK) {
+      delete p;
+      return st;
+    }
+    if (p->cfg.split > 1 && an.K > 0) {
+      const size_t es = compute == FAMLIES_BF16X3 ? 8 : (size_t)an.esize;
+      p->work_bytes = (size_t)p->cfg.split * (size_t)mp * (size_t)np * es;
+      hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
+      if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc(split-K workspace)");
+      }
+    }
+  }
+  register_live(p);
+  *out = p;
+  return FAMLIES_OK;
+}
+
+
 }  // namespace famlies
 
 famlies_plan_s::~famlies_plan_s() {
@@ -270,55 +325,7 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, 
 famlies_status famlies_plan_contract(famlies_handle h, famlies_plan* out, int dtype, int compute,
                                      const famlies_tensor* A, const famlies_tensor* B,
                                      const famlies_tensor* C) {
-  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
-  *out = nullptr;
-  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
-  Analysis an;
-  std::string err;
-  int st = analyze(dtype, compute, A, B, C, &an, &err);
-  if (st != FAMLIES_OK) return fail(st, err);
-  const int64_t lim = ((int64_t)1 << 31) - 1024;
-  if (an.M > lim || an.N > lim || an.K > lim)
-    return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
-  DeviceGuard dg(h->device);
-  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
-  auto* p = new (std::nothrow) famlies_plan_s();
-  if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
-  p->h = h;
-  p->an = an;
-  p->index_bits = index_bits_for(an);
-  p->cfg = choose_tiles(h, an);
-  if (compute == FAMLIES_BF16X3) {
-    p->cfg.bk = 32;
-    if (!bf16x3_tile_supported(p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
-  } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
-    p->cfg.bm = p->cfg.bn = 128;
-    p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
-  }
-  finalize_split(&p->cfg, an.K, &p->kchunk);
-  const bool empty = an.M == 0 || an.N == 0;
-  if (!empty) {
-    const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
-    const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
-    const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
-    st = p->index_bits == 32 ? upload<int32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
-    if (st != FAMLIES_OK) {
-      delete p;
-      return st;
-    }
-    if (p->cfg.split > 1 && an.K > 0) {
-      const size_t es = compute == FAMLIES_BF16X3 ? 8 : (size_t)an.esize;
-      p->work_bytes = (size_t)p->cfg.split * (size_t)mp * (size_t)np * es;
-      hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
-      if (e != hipSuccess) {
-        delete p;
-        return hip_fail(e, "hipMalloc(split-K workspace)");
-      }
-    }
-  }
-  register_live(p);
-  *out = p;
-  return FAMLIES_OK;
+  return make_plan(h, out, dtype, compute, A, B, C, nullptr);
 }
 
 famlies_status famlies_plan_destroy(famlies_plan p) {

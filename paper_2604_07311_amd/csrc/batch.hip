@@ -1,14 +1,163 @@
-// Batched contractions and the autotuner (entry points).
+// Batched contractions: many independent, uneven problems in one persistent
+// launch, and the autotuner that picks tile shapes per size class.
+//
+// The host plans every problem as a single contraction would be planned
+// (labels, grouping, orientation, indexing vectors), then cuts all problems
+// into (problem, tile) work items and deals them to a fixed grid of
+// workgroups: problems are spread over the XCDs by estimated cost (so a
+// problem's tiles share one L2), and inside an XCD items go, largest first,
+// to the least-loaded workgroup (longest-processing-time-first).  The device
+// work list is static, so a launch needs no counters, no atomics and no
+// clearing, and can be captured in a HIP graph and replayed.  This is the
+// on-GPU counterpart of running many tile-sized contractions (Approach,
+// "Supporting tensor computations": tiling of tensors, tensor-of-tensors
+// and dynamic blocking) and of block-size selection per problem (the
+// control tree of Section "Building on important advances").
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <queue>
 #include <string>
+#include <vector>
 
 #include "famlies.h"
 #include "runtime.hpp"
+#include "tile.hpp"
 
 namespace famlies {
-struct BatchPlan {};
+
+struct BatchProblemDev {
+  int32_t M, N, K;
+  int32_t flags;  // bit 0: swapped, bit 1: X gathered along K, bit 2: Y along K, bits 8..: tile class
+  int64_t off;    // first element of this problem's six indexing vectors in the pool
+  int32_t pos[6]; // vector starts relative to off: X rows, X k, Y k, Y cols, C rows, C cols
+};
+
+struct BatchItem {
+  int32_t prob;
+  int16_t tm, tn;
+};
+
+struct BatchArgs {
+  const BatchProblemDev* probs;
+  const BatchItem* items;
+  const int32_t* wg_start;  // items of workgroup w: [wg_start[w], wg_start[w+1])
+  const int32_t* pool;      // indexing vectors
+  const void* const* A;
+  const void* const* B;
+  void* const* C;
+  double alpha, beta;
+};
+
+// Tile classes of the batched kernel (BM = BN; BK fixed per element type).
+constexpr int kBatchClasses = 2;
+__host__ __device__ constexpr int batch_class_tile(int cls) { return cls == 0 ? 64 : 128; }
+
+template <typename T, int BT, bool XK, bool YK>
+__device__ __forceinline__ void run_item(const TileJob<int32_t>& j, T* smem) {
+  constexpr int BK = sizeof(T) == 8 ? 16 : 32;
+  PlainTile<T, BT, BT, BK, XK, YK>::template run<int32_t>(j, smem);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void batch_contract(BatchArgs a) {
+  constexpr int BK = sizeof(T) == 8 ? 16 : 32;
+  constexpr int SM = PlainTile<T, 128, 128, BK, true, true>::SMEM;
+  __shared__ T smem[SM];
+  const int w = blockIdx.x;
+  const int beg = a.wg_start[w], end = a.wg_start[w + 1];
+  for (int it = beg; it < end; ++it) {
+    const BatchItem item = a.items[it];
+    const BatchProblemDev& P = a.probs[item.prob];
+    const int flags = P.flags;
+    const bool swapped = flags & 1;
+    const int cls = flags >> 8;
+    const int bt = cls == 0 ? 64 : 128;
+    const int32_t* o = a.pool + P.off;
+    TileJob<int32_t> j;
+    j.x = swapped ? a.B[item.prob] : a.A[item.prob];
+    j.y = swapped ? a.A[item.prob] : a.B[item.prob];
+    j.c = a.C[item.prob];
+    j.xmn = o + P.pos[0];
+    j.xk = o + P.pos[1];
+    j.yk = o + P.pos[2];
+    j.ymn = o + P.pos[3];
+    j.cm = o + P.pos[4];
+    j.cn = o + P.pos[5];
+    j.M = P.M;
+    j.N = P.N;
+    j.m0 = item.tm * bt;
+    j.n0 = item.tn * bt;
+    j.kbeg = 0;
+    j.kend = P.K;
+    j.alpha = a.alpha;
+    j.beta = a.beta;
+    j.work = nullptr;
+    j.ldw = 0;
+    switch (((flags >> 1) & 3) | (cls << 2)) {
+      case 0: run_item<T, 64, false, false>(j, smem); break;
+      case 1: run_item<T, 64, true, false>(j, smem); break;
+      case 2: run_item<T, 64, false, true>(j, smem); break;
+      case 3: run_item<T, 64, true, true>(j, smem); break;
+      case 4: run_item<T, 128, false, false>(j, smem); break;
+      case 5: run_item<T, 128, true, false>(j, smem); break;
+      case 6: run_item<T, 128, false, true>(j, smem); break;
+      default: run_item<T, 128, true, true>(j, smem); break;
+    }
+    __syncthreads();
+  }
+}
+
+struct BatchPlan {
+  int dtype = FAMLIES_F32;
+  int64_t n = 0;
+  int grid = 0;
+  void* d_buf = nullptr;  // probs | items | wg_start | pool, one allocation
+  BatchArgs args{};
+  int64_t n_items = 0;
+  double flops = 0.0;
+  std::vector<int> scale_only;  // problems with K == 0 (alpha*A.B vanishes)
+  const int32_t* scale_dev = nullptr;
+  ~BatchPlan() {
+    if (d_buf) (void)hipFree(d_buf);
+  }
+};
+
 void destroy_batch(BatchPlan* b) { delete b; }
+
+// Problems whose product term vanishes (K == 0, or every problem when
+// alpha == 0): C = beta * C (beta == 0 writes zeros without reading C).  One
+// workgroup per problem; `list` selects the problems, or all when null.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void batch_scale(BatchArgs a, const int32_t* list, int n) {
+  if ((int)blockIdx.x >= n) return;
+  const int p = list ? list[blockIdx.x] : (int)blockIdx.x;
+  const BatchProblemDev& P = a.probs[p];
+  const int32_t* o = a.pool + P.off;
+  T* C = static_cast<T*>(a.C[p]);
+  const int64_t mn = (int64_t)P.M * P.N;
+  const T be = static_cast<T>(a.beta);
+  for (int64_t i = threadIdx.x; i < mn; i += kThreads) {
+    const int m = (int)(i / P.N), nn = (int)(i % P.N);
+    const int32_t idx = o[P.pos[4] + m] + o[P.pos[5] + nn];
+    C[idx] = be != T(0) ? be * C[idx] : T(0);
+  }
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile class for a problem: the tile table's batched entry for its size class
+// if present, else the larger tile when both M and N fill it.
+static int pick_class(const famlies_handle_s* h, int dtype, const Analysis& an) {
+  TileCfg t;
+  if (h->table.lookup_batch(dtype, an.M, an.N, an.K, &t)) return t.bm >= 128 ? 1 : 0;
+  return (an.M >= 128 && an.N >= 128) ? 1 : 0;
+}
+
 }  // namespace famlies
 
 using namespace famlies;
@@ -17,23 +166,205 @@ extern "C" {
 
 famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype, int64_t n,
                                   const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
-  if (out) *out = nullptr;
-  return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: not available in this build");
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: null output pointer");
+  *out = nullptr;
+  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: invalid handle");
+  if (n < 0 || (n > 0 && (!A || !B || !C))) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: bad arrays");
+  if (n > (1 << 30)) return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: too many problems");
+  auto* bp = new (std::nothrow) BatchPlan();
+  if (!bp) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  bp->dtype = dtype;
+  bp->n = n;
+  std::vector<BatchProblemDev> probs((size_t)n);
+  std::vector<int32_t> pool;
+  std::vector<int64_t> tmp;
+  struct Job {
+    int32_t prob;
+    int16_t tm, tn;
+    double cost;
+  };
+  std::vector<std::vector<Job>> per_prob((size_t)n);
+  std::vector<double> prob_cost((size_t)n, 0.0);
+  const int BK = dtype == FAMLIES_F64 ? 16 : 32;
+  for (int64_t p = 0; p < n; ++p) {
+    Analysis an;
+    std::string err;
+    int st = analyze(dtype, FAMLIES_NATIVE, &A[p], &B[p], &C[p], &an, &err);
+    if (st != FAMLIES_OK) {
+      delete bp;
+      return fail(st, "problem " + std::to_string(p) + ": " + err);
+    }
+    const int64_t lim = (int64_t)1 << 30;
+    if (an.max_abs_x >= lim || an.max_abs_y >= lim || an.max_abs_c >= lim || an.M >= lim || an.N >= lim ||
+        an.K >= lim) {
+      delete bp;
+      return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": too large for the batched kernel");
+    }
+    const int cls = pick_class(h, dtype, an);
+    const int bt = batch_class_tile(cls);
+    BatchProblemDev& d = probs[(size_t)p];
+    d.M = (int32_t)an.M;
+    d.N = (int32_t)an.N;
+    d.K = (int32_t)an.K;
+    d.flags = (an.swapped ? 1 : 0) | (an.x_kfast ? 2 : 0) | (an.y_kfast ? 4 : 0) | (cls << 8);
+    d.off = (int64_t)pool.size();
+    if (an.M == 0 || an.N == 0) continue;  // nothing to write
+    const int64_t mp = cdiv(an.M, bt) * bt, np = cdiv(an.N, bt) * bt;
+    const int64_t kp = cdiv(std::max<int64_t>(an.K, 1), BK) * BK + BK;
+    const std::vector<Mode>* groups[6] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J};
+    const int which[6] = {0, 0, 1, 1, 2, 2};
+    const int64_t len[6] = {an.M, an.K, an.K, an.N, an.M, an.N};
+    const int64_t padded[6] = {mp, kp, kp, np, mp, np};
+    for (int v = 0; v < 6; ++v) {
+      d.pos[v] = (int32_t)(pool.size() - d.off);
+      offsets(*groups[v], which[v], len[v], padded[v], tmp);
+      for (int64_t x : tmp) pool.push_back((int32_t)x);
+    }
+    if (an.K == 0) {
+      bp->scale_only.push_back((int)p);
+      continue;
+    }
+    bp->flops += 2.0 * (double)an.M * (double)an.N * (double)an.K;
+    const int tm = (int)cdiv(an.M, bt), tn = (int)cdiv(an.N, bt);
+    // cost model: MFMA work of the padded tile plus a fixed per-item overhead
+    const double c = (double)bt * bt * (double)(cdiv(an.K, BK) * BK) + 64.0 * bt * bt;
+    for (int jn = 0; jn < tn; ++jn)
+      for (int jm = 0; jm < tm; ++jm) per_prob[(size_t)p].push_back({(int32_t)p, (int16_t)jm, (int16_t)jn, c});
+    prob_cost[(size_t)p] = c * tm * tn;
+  }
+  if (pool.size() >= ((size_t)1 << 31)) {
+    delete bp;
+    return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: indexing vectors exceed 2^31 entries");
+  }
+  // Grid: two workgroups per CU (the kernel's LDS and register budget).
+  const int grid = std::max(8, 2 * h->num_cus);
+  const int per_xcd = grid / 8;
+  // 1) problems -> XCDs, largest first, to the least-loaded XCD
+  std::vector<int64_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return prob_cost[(size_t)a] > prob_cost[(size_t)b]; });
+  std::vector<double> xload(8, 0.0);
+  std::vector<std::vector<Job>> xjobs(8);
+  for (int64_t p : order) {
+    if (per_prob[(size_t)p].empty()) continue;
+    int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+    xload[(size_t)x] += prob_cost[(size_t)p];
+    for (const Job& jb : per_prob[(size_t)p]) xjobs[(size_t)x].push_back(jb);
+  }
+  // 2) inside an XCD: items, largest first, to its least-loaded workgroup
+  //    (workgroup w runs on XCD w % 8)
+  std::vector<std::vector<Job>> wjobs((size_t)grid);
+  for (int x = 0; x < 8; ++x) {
+    auto& js = xjobs[(size_t)x];
+    std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
+    typedef std::pair<double, int> Slot;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int k = 0; k < per_xcd; ++k) heap.push({0.0, x + 8 * k});
+    for (const Job& jb : js) {
+      Slot s = heap.top();
+      heap.pop();
+      wjobs[(size_t)s.second].push_back(jb);
+      heap.push({s.first + jb.cost, s.second});
+    }
+  }
+  std::vector<BatchItem> items;
+  std::vector<int32_t> wg_start((size_t)grid + 1, 0);
+  for (int w = 0; w < grid; ++w) {
+    wg_start[(size_t)w] = (int32_t)items.size();
+    auto& js = wjobs[(size_t)w];
+    // within a workgroup, run a problem's tiles back to back (operand reuse)
+    std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) { return a.prob < b.prob; });
+    for (const Job& jb : js) items.push_back({jb.prob, jb.tm, jb.tn});
+  }
+  wg_start[(size_t)grid] = (int32_t)items.size();
+  bp->grid = grid;
+  bp->n_items = (int64_t)items.size();
+  // one device allocation: probs | items | wg_start | scale list | pool
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t s_probs = align(probs.size() * sizeof(BatchProblemDev) + 1);
+  const size_t s_items = align(items.size() * sizeof(BatchItem) + 1);
+  const size_t s_wg = align(wg_start.size() * sizeof(int32_t));
+  const size_t s_scale = align(bp->scale_only.size() * sizeof(int32_t) + 1);
+  const size_t s_pool = align(pool.size() * sizeof(int32_t) + 1);
+  const size_t total = s_probs + s_items + s_wg + s_scale + s_pool;
+  DeviceGuard dg(h->device);
+  hipError_t e = hipMalloc(&bp->d_buf, total);
+  if (e != hipSuccess) {
+    delete bp;
+    return hip_fail(e, "hipMalloc(batched plan)");
+  }
+  char* base = static_cast<char*>(bp->d_buf);
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data(), probs.data(), probs.size() * sizeof(BatchProblemDev));
+  std::memcpy(host.data() + s_probs, items.data(), items.size() * sizeof(BatchItem));
+  std::memcpy(host.data() + s_probs + s_items, wg_start.data(), wg_start.size() * sizeof(int32_t));
+  std::memcpy(host.data() + s_probs + s_items + s_wg, bp->scale_only.data(),
+              bp->scale_only.size() * sizeof(int32_t));
+  std::memcpy(host.data() + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(int32_t));
+  e = hipMemcpy(bp->d_buf, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    delete bp;
+    return hip_fail(e, "hipMemcpy(batched plan)");
+  }
+  bp->args.probs = reinterpret_cast<const BatchProblemDev*>(base);
+  bp->args.items = reinterpret_cast<const BatchItem*>(base + s_probs);
+  bp->args.wg_start = reinterpret_cast<const int32_t*>(base + s_probs + s_items);
+  bp->args.pool = reinterpret_cast<const int32_t*>(base + s_probs + s_items + s_wg + s_scale);
+  bp->scale_dev = reinterpret_cast<const int32_t*>(base + s_probs + s_items + s_wg);
+  auto* p = new (std::nothrow) famlies_plan_s();
+  if (!p) {
+    delete bp;
+    return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  }
+  p->h = h;
+  p->an.dtype = dtype;
+  p->an.esize = dtype == FAMLIES_F64 ? 8 : 4;
+  p->batch = bp;
+  register_live(p);
+  *out = p;
+  return FAMLIES_OK;
 }
 
 famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta, const void* const* A_dev,
                                      const void* const* B_dev, void* const* C_dev, void* stream) {
-  return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_execute: not available in this build");
-}
-
-famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags) {
-  return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_tune: not available in this build");
-}
-
-famlies_status famlies_load_tune_table(famlies_handle h, const char* table_path) {
-  if (!h || !is_live(h) || !table_path) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_load_tune_table: invalid argument");
-  std::string err;
-  if (!h->table.load(table_path, &err)) return fail(FAMLIES_ERR_INVALID_ARG, err);
+  if (!p || !is_live(p) || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: not a batched plan");
+  BatchPlan* bp = p->batch;
+  if (bp->n == 0) return FAMLIES_OK;
+  if (!A_dev || !B_dev || !C_dev) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: null pointer array");
+  DeviceGuard dg(p->h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the plan's device");
+  BatchArgs a = bp->args;
+  a.A = A_dev;
+  a.B = B_dev;
+  a.C = C_dev;
+  a.alpha = alpha;
+  a.beta = beta;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool f64 = bp->dtype == FAMLIES_F64;
+  if (alpha != 0.0) {
+    if (bp->n_items > 0) {
+      if (f64)
+        hipLaunchKernelGGL(batch_contract<double>, dim3(bp->grid), dim3(kThreads), 0, s, a);
+      else
+        hipLaunchKernelGGL(batch_contract<float>, dim3(bp->grid), dim3(kThreads), 0, s, a);
+    }
+    const int ns = (int)bp->scale_only.size();
+    if (ns > 0) {
+      if (f64)
+        hipLaunchKernelGGL(batch_scale<double>, dim3(ns), dim3(kThreads), 0, s, a, bp->scale_dev, ns);
+      else
+        hipLaunchKernelGGL(batch_scale<float>, dim3(ns), dim3(kThreads), 0, s, a, bp->scale_dev, ns);
+    }
+  } else {
+    const int n = (int)bp->n;
+    if (f64)
+      hipLaunchKernelGGL(batch_scale<double>, dim3(n), dim3(kThreads), 0, s, a, nullptr, n);
+    else
+      hipLaunchKernelGGL(batch_scale<float>, dim3(n), dim3(kThreads), 0, s, a, nullptr, n);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
   return FAMLIES_OK;
 }
 

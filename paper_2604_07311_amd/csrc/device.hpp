@@ -46,7 +46,7 @@ struct Mfma<double> {  // v_mfma_f64_16x16x4_f64
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   // row of accumulator element r held by lane l (column is l % 16)
-  __device__ __forceinline__ static int row(int l, int r) { return 4 * (l / 16) + r; }
+  __device__ __forceinline__ static int row(int l, int r) { return (l / 16) + 4 * r; }
 };
 
 template <>

@@ -8,128 +8,43 @@
 //   ->  alpha/beta scatter-update of C through C's indexing vectors
 // (block-scatter mapping, Approach, "Supporting tensor computations"; the
 // loops-around-a-micro-kernel structure of Fig. "five loops").
-#include "device.hpp"
 #include "launch.hpp"
+#include "tile.hpp"
 
 namespace famlies {
 
 template <typename T, typename OffT, int BM, int BN, int BK, bool XK, bool YK>
 __global__ __launch_bounds__(kThreads) void plain_contract(PlainArgs<OffT> a) {
-  using MF = Mfma<T>;
-  using GX = TileGather<T, OffT, BM, BK, XK>;
-  using GY = TileGather<T, OffT, BN, BK, YK>;
-  constexpr int WTM = BM / 2, WTN = BN / 2;
-  constexpr int MB = WTM / MF::BS, NB = WTN / MF::BS;
-  constexpr int KPG = BK / MF::KG;  // k's per lane group per slice
-  constexpr int XS = BM * GX::LDK, YS = BN * GY::LDK;
-  static_assert(MB >= 1 && NB >= 1 && BK % MF::KG == 0, "bad tile");
-  __shared__ T smem[2 * (XS + YS)];
-
-  const int tid = threadIdx.x;
-  const int lane = tid % 64, wave = tid / 64;
-  const int wm = wave / 2, wn = wave % 2;
-
+  using Tile = PlainTile<T, BM, BN, BK, XK, YK>;
+  __shared__ T smem[Tile::SMEM];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_m * a.tiles_n;
   const int split = lid / ntiles;
   const int t = lid % ntiles;
   const int pm = t % a.tiles_m, pn = t / a.tiles_m;  // M fastest: neighbours share Y's panel
-  const int m0 = pm * BM, n0 = pn * BN;
-  const int kbeg = split * a.kchunk;
-  const int kend = min(a.K, kbeg + a.kchunk);
-  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-
-  const T* __restrict__ X = static_cast<const T*>(a.x);
-  const T* __restrict__ Y = static_cast<const T*>(a.y);
-
-  GX gx;
-  GY gy;
-  gx.init(a.xmn, m0, tid);
-  gy.init(a.ymn, n0, tid);
-
-  typename MF::Acc acc[MB][NB];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = typename MF::Acc{};
-
-  const int g = lane / MF::BS, r = lane % MF::BS;
-  if (nk > 0) {
-    gx.load(X, a.xk, kbeg, kend);
-    gy.load(Y, a.yk, kbeg, kend);
-    gx.store(smem);
-    gy.store(smem + XS);
-    __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int cur = it & 1;
-      const bool more = it + 1 < nk;
-      if (more) {
-        const int kn = kbeg + (it + 1) * BK;
-        gx.load(X, a.xk, kn, kend);
-        gy.load(Y, a.yk, kn, kend);
-      }
-      const T* xs = smem + cur * (XS + YS);
-      const T* ys = xs + XS;
-#pragma unroll
-      for (int s = 0; s < KPG; ++s) {
-        T av[MB], bv[NB];
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-          av[i] = xs[(wm * WTM + i * MF::BS + r) * GX::LDK + g * KPG + s];
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          bv[j] = ys[(wn * WTN + j * MF::BS + r) * GY::LDK + g * KPG + s];
-#pragma unroll
-        for (int i = 0; i < MB; ++i)
-#pragma unroll
-          for (int j = 0; j < NB; ++j) acc[i][j] = MF::mma(av[i], bv[j], acc[i][j]);
-      }
-      if (more) {
-        T* nx = smem + (cur ^ 1) * (XS + YS);
-        gx.store(nx);
-        gy.store(nx + XS);
-      }
-      __syncthreads();
-    }
-  }
-
-  if (a.splits == 1) {
-    T* __restrict__ C = static_cast<T*>(a.c);
-    const T al = static_cast<T>(a.alpha), be = static_cast<T>(a.beta);
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int n = n0 + wn * WTN + j * MF::BS + r;
-      const OffT cn = a.cn[n];
-#pragma unroll
-      for (int i = 0; i < MB; ++i) {
-#pragma unroll
-        for (int e = 0; e < MF::NACC; ++e) {
-          const int m = m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
-          if (m < a.M && n < a.N) {
-            const OffT idx = a.cm[m] + cn;
-            T v = al * acc[i][j][e];
-            if (be != T(0)) v += be * C[idx];
-            C[idx] = v;
-          }
-        }
-      }
-    }
-  } else {
-    // Partial sums of this K range, full padded tile, dense [m][n].
-    const int ldw = a.tiles_n * BN;
-    T* __restrict__ W = static_cast<T*>(a.work) + (size_t)split * (size_t)(a.tiles_m * BM) * ldw;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int n = n0 + wn * WTN + j * MF::BS + r;
-#pragma unroll
-      for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int e = 0; e < MF::NACC; ++e) {
-          const int m = m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
-          W[(size_t)m * ldw + n] = acc[i][j][e];
-        }
-    }
-  }
+  TileJob<OffT> j;
+  j.x = a.x;
+  j.y = a.y;
+  j.c = a.c;
+  j.xmn = a.xmn;
+  j.xk = a.xk;
+  j.yk = a.yk;
+  j.ymn = a.ymn;
+  j.cm = a.cm;
+  j.cn = a.cn;
+  j.M = a.M;
+  j.N = a.N;
+  j.m0 = pm * BM;
+  j.n0 = pn * BN;
+  j.kbeg = split * a.kchunk;
+  j.kend = min(a.K, j.kbeg + a.kchunk);
+  j.alpha = a.alpha;
+  j.beta = a.beta;
+  j.ldw = a.tiles_n * BN;
+  j.work = a.splits == 1 ? nullptr
+                         : static_cast<void*>(static_cast<T*>(a.work) +
+                                              (size_t)split * (size_t)(a.tiles_m * BM) * j.ldw);
+  Tile::run(j, smem);
 }
 
 // C = alpha * sum_s W[s] + beta * C, the K slices summed in index order so

@@ -73,6 +73,10 @@ void register_live(const void* p);
 void unregister_live(const void* p);
 bool is_live(const void* p);
 TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an);
+// Plan one contraction; `force` (may be null) overrides the tile choice.
+famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, int compute,
+                         const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                         const TileCfg* force);
 
 hipError_t launch_bf16x3(const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s);
 hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s);

@@ -1,5 +1,6 @@
 // Tile table: text load/save and lookup by size class.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <fstream>
 #include <sstream>
@@ -14,25 +15,27 @@ int TileTable::log2c(int64_t x) {
   return l;
 }
 
-bool TileTable::lookup_plain(const Analysis& an, TileCfg* out) const {
-  const int lm = log2c(an.M), ln = log2c(an.N), lk = log2c(an.K);
-  for (const Entry& e : entries)
-    if (e.kind == 0 && e.dtype == an.dtype && e.compute == an.compute && e.lm == lm && e.ln == ln &&
-        e.lk == lk) {
+// Nearest tuned class (L1 distance in log2 space, at most 2), if any.
+static bool nearest(const std::vector<TileTable::Entry>& entries, int kind, int dtype, int compute, int lm,
+                    int ln, int lk, TileCfg* out) {
+  int best = 3;
+  for (const TileTable::Entry& e : entries) {
+    if (e.kind != kind || e.dtype != dtype || e.compute != compute) continue;
+    const int d = std::abs(e.lm - lm) + std::abs(e.ln - ln) + std::abs(e.lk - lk);
+    if (d < best) {
+      best = d;
       *out = e.cfg;
-      return true;
     }
-  return false;
+  }
+  return best <= 2;
+}
+
+bool TileTable::lookup_plain(const Analysis& an, TileCfg* out) const {
+  return nearest(entries, 0, an.dtype, an.compute, log2c(an.M), log2c(an.N), log2c(an.K), out);
 }
 
 bool TileTable::lookup_batch(int dtype, int64_t m, int64_t n, int64_t k, TileCfg* out) const {
-  const int lm = log2c(m), ln = log2c(n), lk = log2c(k);
-  for (const Entry& e : entries)
-    if (e.kind == 1 && e.dtype == dtype && e.lm == lm && e.ln == ln && e.lk == lk) {
-      *out = e.cfg;
-      return true;
-    }
-  return false;
+  return nearest(entries, 1, dtype, FAMLIES_NATIVE, log2c(m), log2c(n), log2c(k), out);
 }
 
 void TileTable::put(const Entry& e) {

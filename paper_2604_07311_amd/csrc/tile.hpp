@@ -1,0 +1,143 @@
+// One C tile of the kernel view C(m,n) = sum_k X(m,k) Y(k,n): the body shared
+// by the single-problem kernels and the persistent batched kernel.
+//
+//   gather X, Y K-slices through the indexing vectors into double-buffered LDS
+//   -> 2x2 waves, each a (BM/2)x(BN/2) MFMA tile
+//   -> alpha/beta scatter-update of C, or FP partial sums for split-K
+#pragma once
+
+#include "device.hpp"
+
+namespace famlies {
+
+template <typename OffT>
+struct TileJob {
+  const void* x;
+  const void* y;
+  void* c;
+  const OffT* xmn;
+  const OffT* xk;
+  const OffT* yk;
+  const OffT* ymn;
+  const OffT* cm;
+  const OffT* cn;
+  int M, N;
+  int m0, n0, kbeg, kend;
+  double alpha, beta;
+  void* work;  // non-null: write partial sums here, dense [m][n] with leading dim ldw
+  int ldw;
+};
+
+template <typename T, int BM, int BN, int BK, bool XK, bool YK>
+struct PlainTile {
+  using MF = Mfma<T>;
+  template <typename OffT>
+  using GX = TileGather<T, OffT, BM, BK, XK>;
+  template <typename OffT>
+  using GY = TileGather<T, OffT, BN, BK, YK>;
+  static constexpr int LX = XK ? BK + 16 / (int)sizeof(T) : BK + 1;
+  static constexpr int LY = YK ? BK + 16 / (int)sizeof(T) : BK + 1;
+  static constexpr int XS = BM * LX, YS = BN * LY;
+  static constexpr int SMEM = 2 * (XS + YS);  // elements of T
+  static constexpr int WTM = BM / 2, WTN = BN / 2;
+  static constexpr int MB = WTM / MF::BS, NB = WTN / MF::BS;
+  static constexpr int KPG = BK / MF::KG;
+  static_assert(MB >= 1 && NB >= 1 && BK % MF::KG == 0, "bad tile");
+
+  template <typename OffT>
+  __device__ __forceinline__ static void run(const TileJob<OffT>& j, T* smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid % 64, wave = tid / 64;
+    const int wm = wave / 2, wn = wave % 2;
+    const int nk = j.kend > j.kbeg ? (j.kend - j.kbeg + BK - 1) / BK : 0;
+    const T* __restrict__ X = static_cast<const T*>(j.x);
+    const T* __restrict__ Y = static_cast<const T*>(j.y);
+
+    GX<OffT> gx;
+    GY<OffT> gy;
+    gx.init(j.xmn, j.m0, tid);
+    gy.init(j.ymn, j.n0, tid);
+
+    typename MF::Acc acc[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) acc[i][jj] = typename MF::Acc{};
+
+    const int g = lane / MF::BS, r = lane % MF::BS;
+    if (nk > 0) {
+      gx.load(X, j.xk, j.kbeg, j.kend);
+      gy.load(Y, j.yk, j.kbeg, j.kend);
+      gx.store(smem);
+      gy.store(smem + XS);
+      __syncthreads();
+      for (int it = 0; it < nk; ++it) {
+        const int cur = it & 1;
+        const bool more = it + 1 < nk;
+        if (more) {
+          const int kn = j.kbeg + (it + 1) * BK;
+          gx.load(X, j.xk, kn, j.kend);
+          gy.load(Y, j.yk, kn, j.kend);
+        }
+        const T* xs = smem + cur * (XS + YS);
+        const T* ys = xs + XS;
+#pragma unroll
+        for (int s = 0; s < KPG; ++s) {
+          T av[MB], bv[NB];
+#pragma unroll
+          for (int i = 0; i < MB; ++i) av[i] = xs[(wm * WTM + i * MF::BS + r) * LX + g * KPG + s];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) bv[jj] = ys[(wn * WTN + jj * MF::BS + r) * LY + g * KPG + s];
+#pragma unroll
+          for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) acc[i][jj] = MF::mma(av[i], bv[jj], acc[i][jj]);
+        }
+        if (more) {
+          T* nx = smem + (cur ^ 1) * (XS + YS);
+          gx.store(nx);
+          gy.store(nx + XS);
+        }
+        __syncthreads();
+      }
+    }
+
+    if (j.work == nullptr) {
+      T* __restrict__ C = static_cast<T*>(j.c);
+      const T al = static_cast<T>(j.alpha), be = static_cast<T>(j.beta);
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        const int n = j.n0 + wn * WTN + jj * MF::BS + r;
+        const OffT cn = j.cn[n];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+#pragma unroll
+          for (int e = 0; e < MF::NACC; ++e) {
+            const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
+            if (m < j.M && n < j.N) {
+              const OffT idx = j.cm[m] + cn;
+              T v = al * acc[i][jj][e];
+              if (be != T(0)) v += be * C[idx];
+              C[idx] = v;
+            }
+          }
+        }
+      }
+    } else {
+      T* __restrict__ W = static_cast<T*>(j.work);
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) {
+        const int n = j.n0 + wn * WTN + jj * MF::BS + r;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int e = 0; e < MF::NACC; ++e) {
+            const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
+            W[(size_t)m * j.ldw + n] = acc[i][jj][e];
+          }
+      }
+    }
+  }
+};
+
+}  // namespace famlies

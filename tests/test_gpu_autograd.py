@@ -1,0 +1,109 @@
+"""Hand-written backward (dA, dB as contractions on the same engine):
+gradcheck in FP64, central finite differences in FP64, and the closed-form
+gradients computed by the oracle at o=24, v=96."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.famlies_testutil import check_fp32, check_fp64
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+def _dense(buf, lay):
+    from tests.test_oracle import _as_dense
+    return _as_dense(buf, lay)
+
+
+def test_gradcheck_fp64_tiny():
+    import torch
+    import paper_2604_07311_amd as fm
+    g = torch.Generator().manual_seed(91)
+    A = torch.rand(3, 3, 2, 3, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    B = torch.rand(3, 3, 3, 2, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    C0 = torch.rand(3, 3, 2, 2, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    f = lambda a, b, c: fm.contract_ad(1.3, a, "aeif", b, "ebfj", 0.7, c, "abij")
+    assert torch.autograd.gradcheck(f, (A, B, C0), eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
+def test_backward_matches_oracle_config5():
+    """loss = sum(G * C), C[a,b,i,j] = sum_{e,f} A[a,e,i,f] B[e,b,f,j],
+    o=24, v=96, FP32: dA and dB against the oracle's contractions
+    dA[a,e,i,f] = sum_{b,j} G[a,b,i,j] B[e,b,f,j] and
+    dB[e,b,f,j] = sum_{a,i} A[a,e,i,f] G[a,b,i,j]."""
+    import torch
+    import paper_2604_07311_amd as fm
+    p = synth.autograd_case(24, 96, seed=6)
+    v, o = 96, 24
+    Ah = p.abuf.astype(np.float32)
+    Bh = p.bbuf.astype(np.float32)
+    Gh = p.meta["G"].astype(np.float32)
+    A = torch.from_numpy(Ah).cuda().as_strided((v, v, o, v), p.a.strides).requires_grad_()
+    B = torch.from_numpy(Bh).cuda().as_strided((v, v, v, o), p.b.strides).requires_grad_()
+    G = torch.from_numpy(Gh).cuda().as_strided((v, v, o, o), p.c.strides)
+    note("autograd forward + backward o=24 v=96")
+    C = fm.contract_ad(1.0, A, "aeif", B, "ebfj", 0.0, None, "abij")
+    (C * G).sum().backward()
+    torch.cuda.synchronize()
+    # closed forms by the oracle (FP64 on the FP32 values)
+    Gb = Gh.astype(np.float64)
+    ga = (Gb, 0, p.c.extents, p.c.strides)
+    Bo = (Bh.astype(np.float64), 0, p.b.extents, p.b.strides)
+    Ao = (Ah.astype(np.float64), 0, p.a.extents, p.a.strides)
+    dA_ref, dA_d = oracle.contract(1.0, ga, "abij", Bo, "ebfj", 0.0,
+                                   (np.zeros(p.a.size), 0, p.a.extents, p.a.strides), "aeif",
+                                   want_cond=True)
+    dB_ref, dB_d = oracle.contract(1.0, Ao, "aeif", ga, "abij", 0.0,
+                                   (np.zeros(p.b.size), 0, p.b.extents, p.b.strides), "ebfj",
+                                   want_cond=True)
+    dA = A.grad.cpu().numpy()
+    dB = B.grad.cpu().numpy()
+    # compare in storage order (grads are dense C-order tensors of the view shapes)
+    dA_st = _dense(dA_ref, p.a)
+    dB_st = _dense(dB_ref, p.b)
+    ra = check_fp32(dA.astype(np.float64).ravel(), dA_st.ravel(), _dense(dA_d, p.a).ravel(), v * o)
+    rb = check_fp32(dB.astype(np.float64).ravel(), dB_st.ravel(), _dense(dB_d, p.b).ravel(), v * o)
+    note("dA rel err %.3e, dB rel err %.3e" % (ra, rb))
+
+
+def test_finite_differences_fp64():
+    """The loss is linear in each entry, so a central difference with h = 1
+    has no truncation error: FD and the gradient differ only by the rounding
+    of the two loss evaluations, bounded here by 1e-12 * sum |G| |C|."""
+    import torch
+    import paper_2604_07311_amd as fm
+    o, v = 6, 12
+    g = torch.Generator().manual_seed(92)
+    A = torch.rand(v, v, o, v, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    B = torch.rand(v, v, v, o, generator=g, dtype=torch.float64).cuda().requires_grad_()
+    G = torch.randn(v, v, o, o, generator=g, dtype=torch.float64).cuda()
+
+    def loss(a, b):
+        return (fm.contract_ad(1.0, a, "aeif", b, "ebfj", 0.0, None, "abij") * G).sum()
+
+    L = loss(A, B)
+    L.backward()
+    with torch.no_grad():
+        scale = (fm.contract(1.0, A.detach(), "aeif", B.detach(), "ebfj", 0.0, None, "abij").abs()
+                 * G.abs()).sum().item()
+    tol = 1e-12 * scale
+    rng = np.random.default_rng(93)
+    with torch.no_grad():
+        for _ in range(6):
+            idx = tuple(int(rng.integers(0, s)) for s in A.shape)
+            Ap, Am = A.detach().clone(), A.detach().clone()
+            Ap[idx] += 1.0
+            Am[idx] -= 1.0
+            fd = (loss(Ap, B) - loss(Am, B)).item() / 2.0
+            assert abs(fd - A.grad[idx].item()) <= tol
+            idx = tuple(int(rng.integers(0, s)) for s in B.shape)
+            Bp, Bm = B.detach().clone(), B.detach().clone()
+            Bp[idx] += 1.0
+            Bm[idx] -= 1.0
+            fd = (loss(A, Bp) - loss(A, Bm)).item() / 2.0
+            assert abs(fd - B.grad[idx].item()) <= tol
