@@ -226,6 +226,10 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     }
     bp->flops += 2.0 * (double)an.M * (double)an.N * (double)an.K;
     const int tm = (int)cdiv(an.M, bt), tn = (int)cdiv(an.N, bt);
+    if (tm > 32767 || tn > 32767) {
+      delete bp;
+      return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": more than 32767 tiles along M or N");
+    }
     // cost model: MFMA work of the padded tile plus a fixed per-item overhead
     const double c = (double)bt * bt * (double)(cdiv(an.K, BK) * BK) + 64.0 * bt * bt;
     for (int jn = 0; jn < tn; ++jn)
