@@ -30,10 +30,10 @@ struct SplitLds {
 };
 
 template <typename G, bool KFAST, int LDK>
-__device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo) {
+__device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo, int k0, int kend) {
 #pragma unroll
   for (int j = 0; j < G::E; ++j) {
-    const float x = gg.v[j];
+    const float x = gg.value(j, k0, kend);
     const __bf16 h = static_cast<__bf16>(x);
     const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
     const int idx = KFAST ? (gg.r0 + j * G::RSTEP) * LDK + gg.kk0 : gg.r0 * LDK + gg.kk0 + j * G::KSTEP;
@@ -97,23 +97,32 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
     }
 
   const int g = lane / 32, r = lane % 32;
-  auto stage_store = [&](int buf) {
+  auto stage_store = [&](int buf, int k0) {
     __bf16* base = smem + buf * STAGE;
-    store_split<GX, XK, LX>(gx, base, base + XS);
-    store_split<GY, YK, LY>(gy, base + 2 * XS, base + 2 * XS + YS);
+    store_split<GX, XK, LX>(gx, base, base + XS, k0, kend);
+    store_split<GY, YK, LY>(gy, base + 2 * XS, base + 2 * XS + YS, k0, kend);
   };
   if (nk > 0) {
-    gx.load(X, a.xk, kbeg, kend);
-    gy.load(Y, a.yk, kbeg, kend);
-    stage_store(0);
+    gx.fetch_k(a.xk, kbeg);
+    gy.fetch_k(a.yk, kbeg);
+    gx.load(X);
+    gy.load(Y);
+    if (nk > 1) {
+      gx.fetch_k(a.xk, kbeg + BK);
+      gy.fetch_k(a.yk, kbeg + BK);
+    }
+    stage_store(0, kbeg);
     __syncthreads();
     for (int it = 0; it < nk; ++it) {
       const int cur = it & 1;
       const bool more = it + 1 < nk;
       if (more) {
-        const int kn = kbeg + (it + 1) * BK;
-        gx.load(X, a.xk, kn, kend);
-        gy.load(Y, a.yk, kn, kend);
+        gx.load(X);
+        gy.load(Y);
+        if (it + 2 < nk) {
+          gx.fetch_k(a.xk, kbeg + (it + 2) * BK);
+          gy.fetch_k(a.yk, kbeg + (it + 2) * BK);
+        }
       }
       const __bf16* xh = smem + cur * STAGE;
       const __bf16* xl = xh + XS;
@@ -144,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
             mid[i][j] = mma_bf16(al[i], bh[j], mid[i][j]);
           }
       }
-      if (more) stage_store(cur ^ 1);
+      if (more) stage_store(cur ^ 1, kbeg + (it + 1) * BK);
       __syncthreads();
     }
   }

@@ -68,9 +68,14 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 // KFAST (the operand's smallest stride is a contracted mode): lanes run along
 // k, each thread owns one k column and E rows.  Otherwise lanes run along the
 // rows, each thread owns one row and E k's; those k's are the same for a whole
-// wave when BR is a multiple of 64, so their offsets are wave-uniform loads.
+// wave when BR is a multiple of 64, so their offsets are wave-uniform.
 // Rows past the problem edge carry offset 0 (a valid address) and only feed
-// accumulator rows that are never stored; k's past the edge load as 0.
+// accumulator rows that are never stored; k's past the edge are stored as 0.
+//
+// The three phases are split so a K loop can pipeline them: fetch_k() loads
+// the contracted-index offsets of a future slice, load() issues the data
+// loads of the next slice (no use of the loaded values, so nothing waits on
+// them until store()), store() writes the slice into LDS, zeroing k >= kend.
 template <typename T, typename OffT, int BR, int BK, bool KFAST>
 struct TileGather {
   static constexpr int E = BR * BK / kThreads;
@@ -82,7 +87,8 @@ struct TileGather {
                       : (kThreads % BR == 0 && BK % KSTEP == 0),
                 "tile shape does not divide the workgroup");
 
-  OffT mn[KFAST ? E : 1];
+  OffT mn[KFAST ? E : 1];  // row offsets, fixed for the tile
+  OffT ko[KFAST ? 1 : E];  // contracted-index offsets of the slice to load next
   T v[E];
   int r0, kk0;
 
@@ -100,36 +106,39 @@ struct TileGather {
     }
   }
 
-  __device__ __forceinline__ void load(const T* __restrict__ base, const OffT* __restrict__ koff,
-                                       int k0, int kend) {
+  // Offsets of slice [k0, k0 + BK); koff must hold k0 + BK entries.
+  __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
     if constexpr (KFAST) {
-      const int k = k0 + kk0;
-      const OffT ko = koff[k];
-      const bool ok = k < kend;
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        T t = base[mn[j] + ko];
-        v[j] = ok ? t : T(0);
-      }
+      ko[0] = koff[k0 + kk0];
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int k = k0 + kk0 + j * KSTEP;
-        const OffT ko = koff[k];
-        T t = base[mn[0] + ko];
-        v[j] = k < kend ? t : T(0);
-      }
+      for (int j = 0; j < E; ++j) ko[j] = koff[k0 + kk0 + j * KSTEP];
     }
   }
 
-  __device__ __forceinline__ void store(T* __restrict__ lds) const {
+  __device__ __forceinline__ void load(const T* __restrict__ base) {
     if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) lds[(r0 + j * RSTEP) * LDK + kk0] = v[j];
+      for (int j = 0; j < E; ++j) v[j] = base[mn[j] + ko[0]];
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) lds[r0 * LDK + kk0 + j * KSTEP] = v[j];
+      for (int j = 0; j < E; ++j) v[j] = base[mn[0] + ko[j]];
     }
+  }
+
+  // Value of element j of the slice starting at k0 (0 past kend).
+  __device__ __forceinline__ T value(int j, int k0, int kend) const {
+    const int k = KFAST ? k0 + kk0 : k0 + kk0 + j * KSTEP;
+    return k < kend ? v[j] : T(0);
+  }
+
+  __device__ __forceinline__ int lds_index(int j) const {
+    return KFAST ? (r0 + j * RSTEP) * LDK + kk0 : r0 * LDK + kk0 + j * KSTEP;
+  }
+
+  __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
+#pragma unroll
+    for (int j = 0; j < E; ++j) lds[lds_index(j)] = value(j, k0, kend);
   }
 };
 

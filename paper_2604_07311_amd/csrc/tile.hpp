@@ -66,18 +66,28 @@ struct PlainTile {
 
     const int g = lane / MF::BS, r = lane % MF::BS;
     if (nk > 0) {
-      gx.load(X, j.xk, j.kbeg, j.kend);
-      gy.load(Y, j.yk, j.kbeg, j.kend);
-      gx.store(smem);
-      gy.store(smem + XS);
+      // pipeline: offsets two slices ahead, data one slice ahead, LDS double buffer
+      gx.fetch_k(j.xk, j.kbeg);
+      gy.fetch_k(j.yk, j.kbeg);
+      gx.load(X);
+      gy.load(Y);
+      if (nk > 1) {
+        gx.fetch_k(j.xk, j.kbeg + BK);
+        gy.fetch_k(j.yk, j.kbeg + BK);
+      }
+      gx.store(smem, j.kbeg, j.kend);
+      gy.store(smem + XS, j.kbeg, j.kend);
       __syncthreads();
       for (int it = 0; it < nk; ++it) {
         const int cur = it & 1;
         const bool more = it + 1 < nk;
         if (more) {
-          const int kn = j.kbeg + (it + 1) * BK;
-          gx.load(X, j.xk, kn, j.kend);
-          gy.load(Y, j.yk, kn, j.kend);
+          gx.load(X);
+          gy.load(Y);
+          if (it + 2 < nk) {
+            gx.fetch_k(j.xk, j.kbeg + (it + 2) * BK);
+            gy.fetch_k(j.yk, j.kbeg + (it + 2) * BK);
+          }
         }
         const T* xs = smem + cur * (XS + YS);
         const T* ys = xs + XS;
@@ -95,8 +105,9 @@ struct PlainTile {
         }
         if (more) {
           T* nx = smem + (cur ^ 1) * (XS + YS);
-          gx.store(nx);
-          gy.store(nx + XS);
+          const int kn = j.kbeg + (it + 1) * BK;
+          gx.store(nx, kn, j.kend);
+          gy.store(nx + XS, kn, j.kend);
         }
         __syncthreads();
       }

@@ -92,11 +92,11 @@ famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags)
         for (int lk : lks) {
           const int64_t M = (int64_t)1 << lm, N = (int64_t)1 << ln, K = (int64_t)1 << lk;
           if (M * K > cap || K * N > cap || M * N > cap) continue;
-          // C[m,n] = sum_k A[m,k] B[k,n], A row-major along k (the K-gathered case),
-          // B and C column-major
+          // C[m,n] = sum_k A[m,k] B[k,n]: A and B contiguous along k (the
+          // K-gathered case), C contiguous along n (no operand exchange)
           const int64_t ea[2] = {M, K}, sa[2] = {K, 1};
           const int64_t eb[2] = {K, N}, sb[2] = {1, K};
-          const int64_t ec[2] = {M, N}, sc[2] = {1, M};
+          const int64_t ec[2] = {M, N}, sc[2] = {N, 1};
           const int32_t la[2] = {'m', 'k'}, lb[2] = {'k', 'n'}, lc[2] = {'m', 'n'};
           famlies_tensor A = {2, ea, sa, la}, B = {2, eb, sb, lb}, C = {2, ec, sc, lc};
           Analysis an;
@@ -122,26 +122,27 @@ famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags)
             famlies_plan_s* p = nullptr;
             famlies_status st = make_plan(h, &p, md.dtype, md.compute, &A, &B, &C, &t);
             if (st != FAMLIES_OK) return st;
+            const TileCfg eff = p->cfg;  // split after the planner's rounding
             float ms = 0.f;
             st = time_plan(p, buf, s, reps, &ms);
             (void)famlies_plan_destroy(p);
             if (st != FAMLIES_OK) return st;
             if (ms < best) {
               best = ms;
-              bcfg = t;
+              bcfg = eff;
             }
-            if (t.split == 1 && ms < best_nosplit) {
+            if (eff.split == 1 && ms < best_nosplit) {
               best_nosplit = ms;
-              bns = t;
+              bns = eff;
             }
           }
           TileTable::Entry en;
           en.kind = 0;
           en.dtype = md.dtype;
           en.compute = md.compute;
-          en.lm = lm;
-          en.ln = ln;
-          en.lk = lk;
+          en.lm = TileTable::log2c(an.M);
+          en.ln = TileTable::log2c(an.N);
+          en.lk = TileTable::log2c(an.K);
           en.cfg = bcfg;
           fresh.put(en);
           if (md.compute == FAMLIES_NATIVE) {  // batched kernel: no split-K

@@ -147,3 +147,29 @@ def test_batched_graph_replay():
         note("replay %d ok" % rep)
     del g
     bt.close()
+
+
+def test_autotuner_writes_and_uses_table(tmp_path):
+    """famlies_tune (quick grid) measures the candidate tiles on the device,
+    writes a text table, and plans then take their tiles from it."""
+    import paper_2604_07311_amd as fm
+    h = fm.famlies_create(0)
+    path = str(tmp_path / "tiles.txt")
+    fm.famlies_tune(h, path, 1)
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert rows and all(r[0] in ("plain", "batch") and len(r) == 10 for r in rows)
+    note("tuned %d entries" % len(rows))
+    # a plan in a tuned size class takes the table's tile and split
+    r = next(r for r in rows if r[0] == "plain" and r[1] == "2" and r[2] == "0")
+    lm, ln, lk, bm, split = int(r[3]), int(r[4]), int(r[5]), int(r[6]), int(r[9])
+    M, N, K = 1 << lm, 1 << ln, 1 << lk
+    p = fm.famlies_plan_contract(h, fm.FAMLIES_F32, 0, fm.make_desc([M, K], [K, 1], "mk"),
+                                 fm.make_desc([K, N], [1, K], "kn"), fm.make_desc([M, N], [N, 1], "mn"))
+    info = fm.famlies_plan_get_info(p)
+    assert info["swapped"] == 0
+    assert info["tile_m"] == bm and info["split_k"] == split
+    fm.famlies_plan_destroy(p)
+    h2 = fm.famlies_create(0)
+    fm.famlies_load_tune_table(h2, path)
+    fm.famlies_destroy(h2)
+    fm.famlies_destroy(h)
