@@ -10,9 +10,11 @@
  *
  *     C[c] <- alpha * sum_p A[a(c,p)] * B[b(c,p)] + beta * C[c]
  *
- * over labelled modes.  Every label appears in exactly two of A, B, C: a
- * label in A and C is a row ("I") mode, in B and C a column ("J") mode, in A
- * and B a contracted ("P") mode.  The element with multi-index idx of a
+ * over labelled modes (einsum semantics).  A label in A and C is a row ("I")
+ * mode, in B and C a column ("J") mode, in A and B a contracted ("P") mode;
+ * a label in all three is a batch mode (one independent product per batch
+ * index); a label in only A or only B is summed inside that operand; a label
+ * repeated within A or B selects a diagonal.  The element with multi-index idx of a
  * tensor lives at  base + sum_d idx[d] * strides[d]  (strides in elements,
  * any sign; zero allowed for A and B).  The descriptor shape follows the
  * labelled-mode tensor interfaces the paper points to (TAPP, Approach,
@@ -56,7 +58,7 @@ typedef int32_t famlies_status;
 #define FAMLIES_ERR_INVALID_ARG (-1)    /* null pointer, rank < 0 or > 8, negative extent, bad enum */
 #define FAMLIES_ERR_SHAPE_MISMATCH (-2) /* one label with two different extents */
 #define FAMLIES_ERR_LABEL (-3)          /* C label in neither A nor B, or repeated in C */
-#define FAMLIES_ERR_UNSUPPORTED (-4)    /* valid einsum form not implemented (see below) */
+#define FAMLIES_ERR_UNSUPPORTED (-4)    /* valid input this build does not run (see each call) */
 #define FAMLIES_ERR_ALIAS (-5)          /* C not injective, or C's span overlaps A's/B's */
 #define FAMLIES_ERR_ALIGN (-6)          /* data pointer not aligned to its element size */
 #define FAMLIES_ERR_ALLOC (-7)          /* device allocation failed */
@@ -94,16 +96,19 @@ typedef struct {
 /* What the planner decided (host-side summary of a plan). */
 typedef struct {
   int64_t m, n, k;          /* GEMM sizes: products of I, J and P extents */
+  int64_t batch;            /* product of the batch-mode extents (1 if none) */
   int32_t swapped;          /* 1 when the kernel runs C^T = B^T A^T, so that C's
                                smallest-stride mode lies along the kernel's N */
   int32_t x_kfast, y_kfast; /* 1 when the kernel's left (X) / right (Y) operand
                                is gathered along its contracted modes */
   int32_t n_i, n_j, n_p;    /* mode groups after dropping extent-1 modes and fusing */
+  int32_t n_batch;          /* batch modes (extent > 1) */
+  int32_t n_trace, n_diag;  /* labels summed inside one input; labels repeated in an input */
   int32_t tile_m, tile_n, tile_k;
   int32_t split_k;          /* number of K slices (1 = none) */
   int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
   int32_t kernel;           /* internal kernel variant id */
-  double flops;             /* 2*m*n*k */
+  double flops;             /* 2*batch*m*n*k */
 } famlies_plan_info;
 
 /* Create a handle bound to HIP device `device` (reads the tile table named by
@@ -115,10 +120,11 @@ famlies_status famlies_destroy(famlies_handle h);
  * classify labels; drop extent-1 modes, order and fuse mode groups; choose
  * the orientation and gather directions; build the block-scatter indexing
  * vectors -- the "indexing vectors" of the paper's block-scatter mapping --
- * and upload them; choose tile shape and split-K).  dtype is FAMLIES_F64 or
+ * and upload them; choose tile shape and split-K).  UNSUPPORTED when a GEMM
+ * dimension reaches 2^31 - 1024.  dtype is FAMLIES_F64 or
  * FAMLIES_F32; compute is FAMLIES_NATIVE or (F32 only) FAMLIES_BF16X3.
- * UNSUPPORTED: a label in all three tensors (batch mode), a label in only A
- * or only B (trace), or a label repeated within A or B (diagonal). */
+ * A label summed inside one input is contracted against a zero stride in
+ * the other operand (the product runs over it), so it costs MFMA work. */
 famlies_status famlies_plan_contract(famlies_handle h, famlies_plan *out, int dtype, int compute,
                                      const famlies_tensor *A, const famlies_tensor *B,
                                      const famlies_tensor *C);
@@ -133,11 +139,13 @@ famlies_status famlies_plan_destroy(famlies_plan p);
 famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info *out);
 
 /* Host-only dry run of the planner: fills *info and, if offsets != NULL,
- * writes the six indexing vectors of the kernel view, unpadded and in this
+ * writes the indexing vectors of the kernel view, unpadded and in this
  * order: X rows (m entries), X contracted (k), Y contracted (k), Y columns
- * (n), C rows (m), C columns (n); element (m,k) of X is at
- * X + xrow[m] + xk[k] and so on, where X is A (or B when swapped).
- * offsets_len must be at least 2m + 2k + 2n.  Touches no device. */
+ * (n), C rows (m), C columns (n), then the batch offsets of X, Y and C
+ * (batch entries each); element (m,k) of batch l of X is at
+ * X + xbatch[l] + xrow[m] + xk[k] and so on, where X is A (or B when
+ * swapped).  offsets_len must be at least 2m + 2k + 2n + 3 batch.  Touches
+ * no device. */
 famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor *A,
                                const famlies_tensor *B, const famlies_tensor *C,
                                famlies_plan_info *info, int64_t *offsets, int64_t offsets_len);
@@ -147,7 +155,8 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor *A,
  * (problem, tile) items, tile shapes per size class from the handle's tile
  * table (tiles and orientation as in famlies_plan_contract; each descriptor
  * obeys the same rules).  Tensors of different problems may share memory
- * for A and B; C outputs must be disjoint (not checked). */
+ * for A and B; C outputs must be disjoint (not checked).  Batch modes are
+ * UNSUPPORTED in batched plans. */
 famlies_status famlies_batch_plan(famlies_handle h, famlies_plan *out, int dtype, int64_t n,
                                   const famlies_tensor *A, const famlies_tensor *B,
                                   const famlies_tensor *C);

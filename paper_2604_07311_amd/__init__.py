@@ -56,9 +56,11 @@ class famlies_tensor(ctypes.Structure):
 
 class famlies_plan_info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("batch", ctypes.c_int64),
                 ("swapped", ctypes.c_int32), ("x_kfast", ctypes.c_int32),
                 ("y_kfast", ctypes.c_int32), ("n_i", ctypes.c_int32), ("n_j", ctypes.c_int32),
-                ("n_p", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
+                ("n_p", ctypes.c_int32), ("n_batch", ctypes.c_int32), ("n_trace", ctypes.c_int32),
+                ("n_diag", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
                 ("tile_k", ctypes.c_int32), ("split_k", ctypes.c_int32),
                 ("index_bits", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("flops", ctypes.c_double)]
@@ -188,7 +190,7 @@ def famlies_plan_get_info(plan: int) -> dict:
 def famlies_analyze(dtype: int, compute: int, A: famlies_tensor, B: famlies_tensor,
                     C: famlies_tensor, want_offsets: bool = False):
     """Host-only planner dry run.  Returns (info dict, offsets) where offsets
-    is None or a dict of the six indexing vectors (numpy int64)."""
+    is None or a dict of the nine indexing vectors (numpy int64)."""
     lib = load_library()
     info = famlies_plan_info()
     st = lib.famlies_analyze(dtype, compute, ctypes.byref(A), ctypes.byref(B), ctypes.byref(C),
@@ -197,13 +199,14 @@ def famlies_analyze(dtype: int, compute: int, A: famlies_tensor, B: famlies_tens
     if not want_offsets:
         return info.as_dict(), None
     import numpy as np
-    m, n, k = info.m, info.n, info.k
-    buf = np.zeros(2 * (m + n + k), dtype=np.int64)
+    m, n, k, l = info.m, info.n, info.k, info.batch
+    buf = np.zeros(2 * (m + n + k) + 3 * l, dtype=np.int64)
     st = lib.famlies_analyze(dtype, compute, ctypes.byref(A), ctypes.byref(B), ctypes.byref(C),
                              ctypes.byref(info), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                              buf.size)
     _check(st, "famlies_analyze")
-    names, lens = ["xrow", "xk", "yk", "ycol", "crow", "ccol"], [m, k, k, n, m, n]
+    names = ["xrow", "xk", "yk", "ycol", "crow", "ccol", "xbatch", "ybatch", "cbatch"]
+    lens = [m, k, k, n, m, n, l, l, l]
     out, pos = {}, 0
     for nm, ln in zip(names, lens):
         out[nm] = buf[pos:pos + ln].copy()

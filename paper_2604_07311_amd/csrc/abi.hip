@@ -74,15 +74,15 @@ TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
   if (an.M == 0 || an.N == 0 || an.K == 0) return t;
   if (h && h->table.lookup_plain(an, &t)) return t;
   const int cus = h ? h->num_cus : 256;
-  const int64_t big = ceil_div(an.M, 128) * ceil_div(an.N, 128);
+  const int64_t big = ceil_div(an.M, 128) * ceil_div(an.N, 128) * an.L;
   if (big >= cus / 2) {
     t.bm = t.bn = 128;
   } else {
     t.bm = t.bn = 64;
   }
-  const int64_t tiles = ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn);
+  const int64_t tiles = ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn) * an.L;
   t.split = 1;
-  if (tiles < cus) {
+  if (tiles < cus && an.L == 1) {
     int64_t want = ceil_div(2 * cus, tiles);
     int64_t maxs = std::max<int64_t>(1, an.K / (2 * bk));
     t.split = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 64}));
@@ -111,6 +111,10 @@ static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int 
   info->m = an.M;
   info->n = an.N;
   info->k = an.K;
+  info->batch = an.L;
+  info->n_batch = (int32_t)an.Lm.size();
+  info->n_trace = an.n_trace;
+  info->n_diag = an.n_diag;
   info->swapped = an.swapped;
   info->x_kfast = an.x_kfast;
   info->y_kfast = an.y_kfast;
@@ -123,7 +127,7 @@ static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int 
   info->split_k = t.split;
   info->index_bits = index_bits;
   info->kernel = kernel;
-  info->flops = 2.0 * (double)an.M * (double)an.N * (double)an.K;
+  info->flops = 2.0 * (double)an.L * (double)an.M * (double)an.N * (double)an.K;
 }
 
 static int index_bits_for(const Analysis& an) {
@@ -136,18 +140,21 @@ static int index_bits_for(const Analysis& an) {
 template <typename OffT>
 static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp) {
   const Analysis& an = p->an;
-  std::vector<int64_t> v[6];
+  std::vector<int64_t> v[9];
   offsets(an.I, 0, an.M, mp, v[0]);
   offsets(an.P, 0, an.K, kp, v[1]);
   offsets(an.P, 1, an.K, kp, v[2]);
   offsets(an.J, 1, an.N, np, v[3]);
   offsets(an.I, 2, an.M, mp, v[4]);
   offsets(an.J, 2, an.N, np, v[5]);
+  offsets(an.Lm, 0, an.L, an.L, v[6]);
+  offsets(an.Lm, 1, an.L, an.L, v[7]);
+  offsets(an.Lm, 2, an.L, an.L, v[8]);
   size_t total = 0;
   for (auto& x : v) total += x.size();
   std::vector<OffT> host(total);
   size_t pos = 0;
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 9; ++i) {
     p->off_pos[i] = pos;
     for (int64_t o : v[i]) host[pos++] = (OffT)o;
   }
@@ -172,9 +179,13 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   a.ymn = o + p->off_pos[3];
   a.cm = o + p->off_pos[4];
   a.cn = o + p->off_pos[5];
+  a.xl = o + p->off_pos[6];
+  a.yl = o + p->off_pos[7];
+  a.cl = o + p->off_pos[8];
   a.M = (int32_t)p->an.M;
   a.N = (int32_t)p->an.N;
   a.K = (int32_t)p->an.K;
+  a.L = (int32_t)p->an.L;
   a.tiles_m = (int32_t)ceil_div(p->an.M, p->cfg.bm);
   a.tiles_n = (int32_t)ceil_div(p->an.N, p->cfg.bn);
   a.splits = p->cfg.split;
@@ -196,7 +207,7 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   int st = analyze(dtype, compute, A, B, C, &an, &err);
   if (st != FAMLIES_OK) return fail(st, err);
   const int64_t lim = ((int64_t)1 << 31) - 1024;
-  if (an.M > lim || an.N > lim || an.K > lim)
+  if (an.M > lim || an.N > lim || an.K > lim || an.L > lim)
     return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
   DeviceGuard dg(h->device);
   if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
@@ -213,7 +224,12 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     p->cfg.bm = p->cfg.bn = 128;
     p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
   }
+  if (an.L > 1) p->cfg.split = 1;  // batch modes already multiply the tile count
   finalize_split(&p->cfg, an.K, &p->kchunk);
+  if (ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn) * p->cfg.split * an.L >= ((int64_t)1 << 31)) {
+    delete p;
+    return fail(FAMLIES_ERR_UNSUPPORTED, "the tile grid exceeds 2^31 workgroups");
+  }
   const bool empty = an.M == 0 || an.N == 0;
   if (!empty) {
     const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
@@ -306,14 +322,14 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, 
   finalize_split(&t, an.K, &kchunk);
   fill_info(an, t, index_bits_for(an), 0, info);
   if (offs) {
-    const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N;
+    const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N + 3 * an.L;
     if (offs_len < need) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: offsets buffer too short");
     std::vector<int64_t> v;
     int64_t pos = 0;
-    const std::vector<Mode>* groups[6] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J};
-    const int which[6] = {0, 0, 1, 1, 2, 2};
-    const int64_t len[6] = {an.M, an.K, an.K, an.N, an.M, an.N};
-    for (int i = 0; i < 6; ++i) {
+    const std::vector<Mode>* groups[9] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J, &an.Lm, &an.Lm, &an.Lm};
+    const int which[9] = {0, 0, 1, 1, 2, 2, 0, 1, 2};
+    const int64_t len[9] = {an.M, an.K, an.K, an.N, an.M, an.N, an.L, an.L, an.L};
+    for (int i = 0; i < 9; ++i) {
       offsets(*groups[i], which[i], len[i], len[i], v);
       std::copy(v.begin(), v.end(), offs + pos);
       pos += len[i];

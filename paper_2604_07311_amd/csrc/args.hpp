@@ -16,7 +16,10 @@ struct PlainArgs {
   const OffT* ymn;  // Y columns (N, padded)
   const OffT* cm;   // C rows (M, padded)
   const OffT* cn;   // C columns (N, padded)
-  int32_t M, N, K;
+  const OffT* xl;   // batch offsets of X, Y, C (L entries each)
+  const OffT* yl;
+  const OffT* cl;
+  int32_t M, N, K, L;
   int32_t tiles_m, tiles_n, splits, kchunk;
   double alpha, beta;
   void* work;       // split-K partials [splits][tiles_m*BM][tiles_n*BN]

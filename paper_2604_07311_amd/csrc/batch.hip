@@ -194,6 +194,10 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
       delete bp;
       return fail(st, "problem " + std::to_string(p) + ": " + err);
     }
+    if (an.L > 1) {
+      delete bp;
+      return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": batch modes in a batched plan");
+    }
     const int64_t lim = (int64_t)1 << 30;
     if (an.max_abs_x >= lim || an.max_abs_y >= lim || an.max_abs_c >= lim || an.M >= lim || an.N >= lim ||
         an.K >= lim) {

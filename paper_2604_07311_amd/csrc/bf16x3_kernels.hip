@@ -70,8 +70,11 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
   const int tid = threadIdx.x;
   const int lane = tid % 64, wave = tid / 64;
   const int wm = wave / 2, wn = wave % 2;
-  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int lid0 = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_m * a.tiles_n;
+  const int per_batch = ntiles * a.splits;
+  const int l = lid0 / per_batch;  // batch index
+  const int lid = lid0 % per_batch;
   const int split = lid / ntiles;
   const int t = lid % ntiles;
   const int pm = t % a.tiles_m, pn = t / a.tiles_m;
@@ -79,8 +82,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
   const int kbeg = split * a.kchunk;
   const int kend = min(a.K, kbeg + a.kchunk);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  const float* __restrict__ X = static_cast<const float*>(a.x);
-  const float* __restrict__ Y = static_cast<const float*>(a.y);
+  const float* __restrict__ X = static_cast<const float*>(a.x) + a.xl[l];
+  const float* __restrict__ Y = static_cast<const float*>(a.y) + a.yl[l];
 
   GX gx;
   GY gy;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
   }
 
   if (a.splits == 1) {
-    float* __restrict__ C = static_cast<float*>(a.c);
+    float* __restrict__ C = static_cast<float*>(a.c) + a.cl[l];
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int n = n0 + wn * WTN + j * 32 + r;
@@ -225,7 +228,7 @@ static hipError_t launch_b3_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int
 
 template <typename OffT>
 static hipError_t launch_b3(const PlainArgs<OffT>& a, const PlainLaunch& L, hipStream_t s) {
-  const int grid = a.tiles_m * a.tiles_n * a.splits;
+  const int grid = a.tiles_m * a.tiles_n * a.splits * a.L;
   hipError_t e = hipErrorInvalidValue;
   if (L.bm == 128 && L.bn == 128)
     e = launch_b3_tile<OffT, 128, 128>(a, L.xk, L.yk, grid, s);

@@ -25,16 +25,24 @@ struct Mode {
 // at c + cm[m] + cn[n]; each offset vector is the column-major odometer over
 // its group's modes (first mode fastest), the same order for every operand
 // holding the group (conformal partitioning).
+//
+// Labels that are not in exactly two tensors are folded into the same view:
+// a label in all three tensors is a batch ("L") mode -- one independent GEMM
+// per batch index, addressed through three more offset vectors; a label in
+// only one input is summed inside the product, i.e. a contracted mode whose
+// stride in the other input is 0; a label repeated within one input selects
+// the diagonal, i.e. one mode whose stride is the sum of the repeats'.
 struct Analysis {
   int dtype = 0, compute = 0;
-  int64_t M = 0, N = 0, K = 0;
+  int64_t M = 0, N = 0, K = 0, L = 1;
   bool swapped = false;
   bool x_kfast = true, y_kfast = true;
-  std::vector<Mode> I, J, P;
+  std::vector<Mode> I, J, P, Lm;
   // address spans (element offsets relative to the base pointer) of the user
   // tensors A, B, C: [lo, hi]; empty tensors have lo > hi.
   int64_t a_lo = 0, a_hi = -1, b_lo = 0, b_hi = -1, c_lo = 0, c_hi = -1;
   int64_t max_abs_x = 0, max_abs_y = 0, max_abs_c = 0;  // bounds on |offset sums|
+  int n_trace = 0, n_diag = 0;  // labels summed inside one input / repeated in an input
   int esize = 8;
 };
 

@@ -11,21 +11,31 @@
 #include "launch.hpp"
 #include "tile.hpp"
 
+// Two workgroups per CU (waves per SIMD) for the plain kernels: the FP64 tile
+// then keeps its accumulators in VGPRs within 256 registers, and a second
+// workgroup hides the other's barrier and global-load latency.
+#ifndef FAMLIES_PLAIN_WAVES_PER_EU
+#define FAMLIES_PLAIN_WAVES_PER_EU 2
+#endif
+
 namespace famlies {
 
 template <typename T, typename OffT, int BM, int BN, int BK, bool XK, bool YK>
-__global__ __launch_bounds__(kThreads) void plain_contract(PlainArgs<OffT> a) {
+__global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_contract(PlainArgs<OffT> a) {
   using Tile = PlainTile<T, BM, BN, BK, XK, YK>;
   __shared__ T smem[Tile::SMEM];
-  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int lid0 = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_m * a.tiles_n;
+  const int per_batch = ntiles * a.splits;
+  const int l = lid0 / per_batch;  // batch index
+  const int lid = lid0 % per_batch;
   const int split = lid / ntiles;
   const int t = lid % ntiles;
   const int pm = t % a.tiles_m, pn = t / a.tiles_m;  // M fastest: neighbours share Y's panel
   TileJob<OffT> j;
-  j.x = a.x;
-  j.y = a.y;
-  j.c = a.c;
+  j.x = static_cast<const T*>(a.x) + a.xl[l];
+  j.y = static_cast<const T*>(a.y) + a.yl[l];
+  j.c = static_cast<T*>(a.c) + a.cl[l];
   j.xmn = a.xmn;
   j.xk = a.xk;
   j.yk = a.yk;
@@ -66,14 +76,17 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce(PlainArgs<OffT> a, int
   C[idx] = v;
 }
 
-// K == 0: C = beta * C (beta == 0 writes zeros without reading C).
+// K == 0 or alpha == 0: C = beta * C (beta == 0 writes zeros without reading C).
 template <typename T, typename OffT>
 __global__ __launch_bounds__(kThreads) void scale_c(PlainArgs<OffT> a) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= (int64_t)a.M * a.N) return;
-  const int m = (int)(i / a.N), n = (int)(i % a.N);
+  const int64_t mn = (int64_t)a.M * a.N;
+  if (i >= mn * a.L) return;
+  const int l = (int)(i / mn);
+  const int64_t r = i % mn;
+  const int m = (int)(r / a.N), n = (int)(r % a.N);
   T* C = static_cast<T*>(a.c);
-  const OffT idx = a.cm[m] + a.cn[n];
+  const OffT idx = a.cl[l] + a.cm[m] + a.cn[n];
   const T be = static_cast<T>(a.beta);
   C[idx] = be != T(0) ? be * C[idx] : T(0);
 }
@@ -97,10 +110,11 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   const int64_t mn = (int64_t)a.M * a.N;
   const int eg = (int)((mn + kThreads - 1) / kThreads);
   if (L.kind == PlainLaunch::kScale) {
-    hipLaunchKernelGGL((scale_c<T, OffT>), dim3(eg), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((scale_c<T, OffT>), dim3((int)((mn * a.L + kThreads - 1) / kThreads)), dim3(kThreads),
+                       0, s, a);
     return hipGetLastError();
   }
-  const int grid = a.tiles_m * a.tiles_n * a.splits;
+  const int grid = a.tiles_m * a.tiles_n * a.splits * a.L;
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
   hipError_t e = hipErrorInvalidValue;
   if (L.bm == 128 && L.bn == 128 && L.bk == BK)

@@ -42,12 +42,6 @@ bool check_tensor(const famlies_tensor* t, const char* name, std::string* err) {
   return true;
 }
 
-int find(const famlies_tensor* t, int32_t label) {
-  for (int d = 0; d < t->rank; ++d)
-    if (t->labels[d] == label) return d;
-  return -1;
-}
-
 bool repeated(const famlies_tensor* t) {
   for (int d = 0; d < t->rank; ++d)
     for (int e = 0; e < d; ++e)
@@ -143,59 +137,56 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
     *err = "a label is repeated within C";
     return FAMLIES_ERR_LABEL;
   }
-  if (repeated(A) || repeated(B)) {
-    *err = "a label repeated within A or B (diagonal) is not supported";
-    return FAMLIES_ERR_UNSUPPORTED;
-  }
   Analysis an;
   an.dtype = dtype;
   an.compute = compute;
   an.esize = dtype == FAMLIES_F64 ? 8 : 4;
-  std::vector<Mode> I, J, P;  // in user orientation: sx = A stride, sy = B stride
-  for (int d = 0; d < C->rank; ++d) {
-    int32_t l = C->labels[d];
-    int ia = find(A, l), ib = find(B, l);
-    if (ia >= 0 && ib >= 0) {
-      *err = "a label in A, B and C (batch mode) is not supported";
-      return FAMLIES_ERR_UNSUPPORTED;
+  // Distinct labels with their extent and summed stride in each tensor
+  // (summing the strides of a repeated label addresses its diagonal).
+  struct Lab {
+    int32_t label;
+    int64_t ext;
+    int64_t s[3];
+    int cnt[3];
+  };
+  std::vector<Lab> labs;
+  const famlies_tensor* T3[3] = {A, B, C};
+  for (int t = 0; t < 3; ++t) {
+    for (int d = 0; d < T3[t]->rank; ++d) {
+      const int32_t l = T3[t]->labels[d];
+      const int64_t e = T3[t]->extents[d];
+      Lab* f = nullptr;
+      for (Lab& x : labs)
+        if (x.label == l) f = &x;
+      if (!f) {
+        labs.push_back({l, e, {0, 0, 0}, {0, 0, 0}});
+        f = &labs.back();
+      } else if (f->ext != e) {
+        *err = "one label has two different extents";
+        return FAMLIES_ERR_SHAPE_MISMATCH;
+      }
+      f->s[t] += T3[t]->strides[d];
+      f->cnt[t] += 1;
     }
-    if (ia < 0 && ib < 0) {
+  }
+  std::vector<Mode> I, J, P, Lm;  // in user orientation: sx = A stride, sy = B stride
+  for (const Lab& x : labs) {
+    const bool a = x.cnt[0] > 0, b = x.cnt[1] > 0, c = x.cnt[2] > 0;
+    if (x.cnt[0] > 1 || x.cnt[1] > 1) an.n_diag++;
+    Mode m{x.label, x.ext, x.s[0], x.s[1], x.s[2]};
+    if (c && !a && !b) {
       *err = "a label of C appears in neither A nor B";
       return FAMLIES_ERR_LABEL;
     }
-    if (ia >= 0) {
-      if (A->extents[ia] != C->extents[d]) {
-        *err = "extent mismatch between A and C";
-        return FAMLIES_ERR_SHAPE_MISMATCH;
-      }
-      I.push_back({l, C->extents[d], A->strides[ia], 0, C->strides[d]});
-    } else {
-      if (B->extents[ib] != C->extents[d]) {
-        *err = "extent mismatch between B and C";
-        return FAMLIES_ERR_SHAPE_MISMATCH;
-      }
-      J.push_back({l, C->extents[d], 0, B->strides[ib], C->strides[d]});
-    }
-  }
-  for (int d = 0; d < A->rank; ++d) {
-    int32_t l = A->labels[d];
-    if (find(C, l) >= 0) continue;
-    int ib = find(B, l);
-    if (ib < 0) {
-      *err = "a label only in A (trace) is not supported";
-      return FAMLIES_ERR_UNSUPPORTED;
-    }
-    if (B->extents[ib] != A->extents[d]) {
-      *err = "extent mismatch between A and B";
-      return FAMLIES_ERR_SHAPE_MISMATCH;
-    }
-    P.push_back({l, A->extents[d], A->strides[d], B->strides[ib], 0});
-  }
-  for (int d = 0; d < B->rank; ++d) {
-    int32_t l = B->labels[d];
-    if (find(C, l) < 0 && find(A, l) < 0) {
-      *err = "a label only in B (trace) is not supported";
-      return FAMLIES_ERR_UNSUPPORTED;
+    if (a && b && c)
+      Lm.push_back(m);
+    else if (a && c)
+      I.push_back(m);
+    else if (b && c)
+      J.push_back(m);
+    else {
+      if (!(a && b)) an.n_trace++;  // summed inside one input: zero stride in the other
+      P.push_back(m);
     }
   }
   if (!injective(C)) {
@@ -211,7 +202,7 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
     for (const Mode& m : g) p *= m.ext;
     return p;
   };
-  int64_t M = prod(I), N = prod(J), K = prod(P);
+  int64_t M = prod(I), N = prod(J), K = prod(P), L = prod(Lm);
 
   // Drop extent-1 modes (offset always 0).  Extent-0 modes stay so the
   // products remain 0; such problems never reach a kernel.
@@ -221,6 +212,7 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   drop1(I);
   drop1(J);
   drop1(P);
+  drop1(Lm);
 
   // Orientation: the kernel's N runs along the MFMA lane index, so C's
   // smallest-stride mode should be a column mode.  If it is a row mode,
@@ -233,6 +225,7 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
     for (Mode& m : I) std::swap(m.sx, m.sy);
     for (Mode& m : J) std::swap(m.sx, m.sy);
     for (Mode& m : P) std::swap(m.sx, m.sy);
+    for (Mode& m : Lm) std::swap(m.sx, m.sy);
   }
 
   // Order: rows and columns by C's stride; contracted modes by the operand
@@ -253,17 +246,20 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   an.I = fuse(I, 0, 2);
   an.J = fuse(J, 1, 2);
   an.P = fuse(P, 0, 1);
+  std::stable_sort(Lm.begin(), Lm.end(), by(2, 0));
+  an.Lm = Lm;  // batch modes: not fused (one offset per batch index in each operand)
   an.M = M;
   an.N = N;
   an.K = K;
+  an.L = L;
 
   // Gather direction per operand: along the contracted modes when one of them
   // has the operand's smallest stride (ties go to K, the LDS-contiguous way).
   an.x_kfast = an.P.empty() ? false : (an.I.empty() || min_abs(an.P, 0) <= min_abs(an.I, 0));
   an.y_kfast = an.P.empty() ? false : (an.J.empty() || min_abs(an.P, 1) <= min_abs(an.J, 1));
-  an.max_abs_x = reach(an.I, 0) + reach(an.P, 0);
-  an.max_abs_y = reach(an.J, 1) + reach(an.P, 1);
-  an.max_abs_c = reach(an.I, 2) + reach(an.J, 2);
+  an.max_abs_x = reach(an.I, 0) + reach(an.P, 0) + reach(an.Lm, 0);
+  an.max_abs_y = reach(an.J, 1) + reach(an.P, 1) + reach(an.Lm, 1);
+  an.max_abs_c = reach(an.I, 2) + reach(an.J, 2) + reach(an.Lm, 2);
   *out = an;
   return FAMLIES_OK;
 }

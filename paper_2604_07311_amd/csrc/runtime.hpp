@@ -50,8 +50,8 @@ struct famlies_plan_s {
   famlies::TileCfg cfg;
   int index_bits = 32;
   int kchunk = 0;
-  void* d_off = nullptr;   // six indexing vectors, back to back
-  size_t off_pos[6] = {0, 0, 0, 0, 0, 0};
+  void* d_off = nullptr;   // nine indexing vectors, back to back
+  size_t off_pos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   void* d_work = nullptr;  // split-K partial sums
   size_t work_bytes = 0;
   famlies::BatchPlan* batch = nullptr;  // set for batched plans

@@ -110,6 +110,20 @@ def test_block_scatter_vectors_cover_tensors(fm, seed):
     _check_offsets(fm, p)
 
 
+def _kernel_view_numpy(fm, p):
+    """The kernel view's batched GEMM run with numpy through the planner's
+    indexing vectors: C(l,m,n) = alpha sum_k X(l,m,k) Y(l,k,n) + beta C."""
+    info, off = analyze(fm, p, offsets=True)
+    Xb, Xl, Yb, Yl = (p.bbuf, p.b, p.abuf, p.a) if info["swapped"] else (p.abuf, p.a, p.bbuf, p.b)
+    out = p.cbuf.copy()
+    for l in range(info["batch"]):
+        Xm = Xb[Xl.base + off["xbatch"][l] + off["xrow"][:, None] + off["xk"][None, :]]
+        Ym = Yb[Yl.base + off["ybatch"][l] + off["yk"][:, None] + off["ycol"][None, :]]
+        cidx = p.c.base + off["cbatch"][l] + off["crow"][:, None] + off["ccol"][None, :]
+        out[cidx] = p.alpha * (Xm @ Ym) + p.beta * p.cbuf[cidx]
+    return info, out
+
+
 @pytest.mark.parametrize("seed", range(10))
 def test_block_scatter_gemm_equals_oracle(fm, oracle_lib, seed):
     """Running the kernel view's GEMM with numpy through the planner's
@@ -118,15 +132,40 @@ def test_block_scatter_gemm_equals_oracle(fm, oracle_lib, seed):
     rng = np.random.default_rng(600 + seed)
     p = synth.random_problem(rng, lo=1, hi=6, pad_hi=2)
     p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
-    info, off = analyze(fm, p, offsets=True)
-    Xb, Xl, Yb, Yl = (p.bbuf, p.b, p.abuf, p.a) if info["swapped"] else (p.abuf, p.a, p.bbuf, p.b)
-    Xm = Xb[Xl.base + off["xrow"][:, None] + off["xk"][None, :]]
-    Ym = Yb[Yl.base + off["yk"][:, None] + off["ycol"][None, :]]
-    out = p.cbuf.copy()
-    cidx = p.c.base + off["crow"][:, None] + off["ccol"][None, :]
-    out[cidx] = p.alpha * (Xm @ Ym) + p.beta * p.cbuf[cidx]
+    _, out = _kernel_view_numpy(fm, p)
     want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
     np.testing.assert_array_equal(out, want)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_general_labels_kernel_view_equals_oracle(fm, oracle_lib, seed):
+    """Batch labels (in A, B and C), labels summed inside one input and
+    repeated labels (diagonals): the planner's kernel view, run with numpy,
+    equals the oracle's einsum semantics exactly on integer data."""
+    import oracle
+    from tests.test_oracle import _random_roles_problem
+    rng = np.random.default_rng(700 + seed)
+    la, a, lb, b, lc, c = _random_roles_problem(rng, allow_general=True, max_ext=3)
+    p = synth.Problem("gen", la, lb, lc, a, b, c, 1.5, -0.5)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    try:
+        info, out = _kernel_view_numpy(fm, p)
+    except fm.FamliesError as e:   # only C-side problems may be rejected here
+        assert e.code in (fm.FAMLIES_ERR_ALIAS,), e
+        return
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    np.testing.assert_array_equal(out, want)
+
+
+def test_general_label_classification(fm):
+    # batch label b in all three, trace label t only in A, diagonal ii in B
+    A = fm.make_desc([4, 3, 5, 2], [1, 4, 12, 60], "bikt")
+    B = fm.make_desc([4, 5, 6, 6], [1, 4, 20, 21], "bkjj")
+    C = fm.make_desc([4, 3, 6], [1, 4, 12], "bij")
+    info, _ = fm.famlies_analyze(fm.FAMLIES_F64, 0, A, B, C)
+    assert info["batch"] == 4 and info["n_batch"] == 1
+    assert info["n_trace"] == 1 and info["n_diag"] == 1
+    assert sorted((info["m"], info["n"])) == [3, 6] and info["k"] == 10   # k = 5 (k) * 2 (t)
 
 
 def test_negative_and_zero_strides_offsets(fm):
@@ -151,9 +190,7 @@ def test_error_codes(fm):
     assert _err(fm, "ik", "kj", "ij", [2, 3], [4, 5], [2, 5]) == fm.FAMLIES_ERR_SHAPE_MISMATCH
     assert _err(fm, "ik", "kj", "iz", [2, 3], [3, 5], [2, 5]) == fm.FAMLIES_ERR_LABEL
     assert _err(fm, "ik", "kj", "ii", [2, 3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_LABEL
-    assert _err(fm, "bik", "bkj", "bij", [2, 2, 3], [2, 3, 2], [2, 2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
-    assert _err(fm, "ikt", "kj", "ij", [2, 3, 2], [3, 2], [2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
-    assert _err(fm, "iik", "kj", "ij", [2, 2, 3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_UNSUPPORTED
+    assert _err(fm, "iik", "kj", "ij", [2, 3, 3], [3, 2], [2, 2]) == fm.FAMLIES_ERR_SHAPE_MISMATCH
     assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2], sc=[1, 1]) == fm.FAMLIES_ERR_ALIAS
     assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2], dtype=7) == fm.FAMLIES_ERR_INVALID_ARG
     assert _err(fm, "ik", "kj", "ij", [2, 3], [3, 2], [2, 2],

@@ -219,3 +219,51 @@ def test_torch_level_contract(gpu):
     C = fm.contract(1.0, A, "kil", B, "klj", 0.0, None, "ij")
     ref = torch.einsum("kil,klj->ij", A.cpu(), B.cpu())
     torch.testing.assert_close(C.cpu(), ref, rtol=1e-13, atol=1e-13)
+
+
+def _general_problem(rng, max_ext):
+    """Random labels in every role: row, column, contracted, batch (in all
+    three), summed inside one input, and a diagonal (repeated label)."""
+    from tests.test_oracle import _random_roles_problem
+    while True:
+        la, a, lb, b, lc, c = _random_roles_problem(rng, allow_general=True, max_ext=max_ext)
+        if a.size < 4_000_000 and b.size < 4_000_000 and c.size < 4_000_000:
+            return synth.Problem("general", la, lb, lc, a, b, c, 1.5, -0.5)
+
+
+@pytest.mark.parametrize("compute", ["f64", "f32", "bf16x3"])
+@pytest.mark.parametrize("seed", range(10))
+def test_general_labels_integer_exact(gpu, compute, seed):
+    """Batch labels, labels summed inside one input and diagonals, on
+    random layouts: integer data, so every path equals the oracle bit for bit."""
+    import paper_2604_07311_amd as fm
+    rng = np.random.default_rng(9300 + seed)
+    p = _general_problem(rng, max_ext=12)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    dtype = "f64" if compute == "f64" else "f32"
+    comp = "bf16x3" if compute == "bf16x3" else "native"
+    try:
+        plan = gpu.plan(p, dtype, comp)
+    except fm.FamliesError as e:
+        assert e.code == fm.FAMLIES_ERR_ALIAS   # non-injective random C layouts
+        return
+    info = fm.famlies_plan_get_info(plan)
+    note("general %s seed %d: %s%s%s batch=%d trace=%d diag=%d" % (
+        compute, seed, p.la, ",", p.lb, info["batch"], info["n_trace"], info["n_diag"]))
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    got = gpu.run(p, dtype, compute=comp, plan=plan)
+    fm.famlies_plan_destroy(plan)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_mode_real(gpu, dtype):
+    """C[b,a,i] = sum_e A[a,e,b] B[e,i,b]: a batch label over several tiles."""
+    a = synth.layout([70, 90, 5], order=[1, 0, 2])
+    b = synth.layout([90, 130, 5], pad=[1, 0, 0])
+    c = synth.layout([5, 70, 130], order=[2, 1, 0])
+    p = synth.Problem("batchmode", "aeb", "eib", "bai", a, b, c, 1.0, 0.5)
+    rng = np.random.default_rng(9400)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
+    note("batch mode %s" % dtype)
+    _parity(gpu, p, dtype)
