@@ -130,13 +130,19 @@ static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int 
   info->flops = 2.0 * (double)an.L * (double)an.M * (double)an.N * (double)an.K;
 }
 
+// 32: uint32 byte offsets from each operand's lowest element (every operand
+// spans less than 4 GiB over its non-batch modes); 64: int64 element offsets.
 static int index_bits_for(const Analysis& an) {
-  const int64_t lim = (int64_t)1 << 30;
-  return (an.max_abs_x < lim && an.max_abs_y < lim && an.max_abs_c < lim) ? 32 : 64;
+  const int64_t lim = ((int64_t)1 << 32) - 64;
+  const int64_t es = an.esize;
+  return ((an.x_span + 1) * es < lim && (an.y_span + 1) * es < lim && (an.c_span + 1) * es < lim) ? 32 : 64;
 }
 
-// Upload the six indexing vectors (padded to the tile grid) into one device
-// buffer of OffT.
+// Upload the indexing vectors (padded to the tile grid) into one device
+// buffer: six OffT vectors (X rows, X k, Y k, Y cols, C rows, C cols), then
+// the three int64 batch-offset vectors.  In the uint32 form every row vector
+// is rebased by its operand's lowest offset and all six are scaled to bytes;
+// sums row + col then land in [0, span) (unsigned wrap-around is exact).
 template <typename OffT>
 static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp) {
   const Analysis& an = p->an;
@@ -150,17 +156,34 @@ static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t 
   offsets(an.Lm, 0, an.L, an.L, v[6]);
   offsets(an.Lm, 1, an.L, an.L, v[7]);
   offsets(an.Lm, 2, an.L, an.L, v[8]);
-  size_t total = 0;
-  for (auto& x : v) total += x.size();
-  std::vector<OffT> host(total);
+  const bool bytes = sizeof(OffT) == 4;
+  const int64_t es = an.esize;
+  const int64_t shift[6] = {an.x_lo, 0, 0, an.y_lo, an.c_lo_mn, 0};
+  size_t n6 = 0;
+  for (int i = 0; i < 6; ++i) n6 += v[i].size();
+  const size_t b6 = (n6 * sizeof(OffT) + 7) & ~(size_t)7;
+  const size_t total = b6 + 3 * (size_t)an.L * sizeof(int64_t);
+  std::vector<char> host(total, 0);
+  OffT* o = reinterpret_cast<OffT*>(host.data());
   size_t pos = 0;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 6; ++i) {
     p->off_pos[i] = pos;
-    for (int64_t o : v[i]) host[pos++] = (OffT)o;
+    for (int64_t x : v[i]) {
+      if (bytes)
+        o[pos++] = (OffT)(uint64_t)((x - shift[i]) * es);  // wraps modulo 2^32 on purpose
+      else
+        o[pos++] = (OffT)x;
+    }
   }
-  hipError_t e = hipMalloc(&p->d_off, total * sizeof(OffT));
+  int64_t* lb = reinterpret_cast<int64_t*>(host.data() + b6);
+  for (int i = 0; i < 3; ++i) {
+    p->off_pos[6 + i] = (size_t)i * (size_t)an.L;
+    for (int64_t l = 0; l < an.L; ++l) lb[i * an.L + l] = v[6 + i][(size_t)l];
+  }
+  p->batch_off_bytes = b6;
+  hipError_t e = hipMalloc(&p->d_off, total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(indexing vectors)");
-  e = hipMemcpy(p->d_off, host.data(), total * sizeof(OffT), hipMemcpyHostToDevice);
+  e = hipMemcpy(p->d_off, host.data(), total, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(indexing vectors)");
   return FAMLIES_OK;
 }
@@ -170,18 +193,22 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
                                  double alpha, double beta) {
   PlainArgs<OffT> a;
   const OffT* o = static_cast<const OffT*>(p->d_off);
-  a.x = x;
-  a.y = y;
-  a.c = c;
+  const int64_t* lb = reinterpret_cast<const int64_t*>(static_cast<const char*>(p->d_off) + p->batch_off_bytes);
+  const bool bytes = sizeof(OffT) == 4;
+  const int64_t es = p->an.esize;
+  // in the byte form the kernel addresses each operand from its lowest element
+  a.x = x ? static_cast<const char*>(x) + (bytes ? p->an.x_lo * es : 0) : nullptr;
+  a.y = y ? static_cast<const char*>(y) + (bytes ? p->an.y_lo * es : 0) : nullptr;
+  a.c = static_cast<char*>(c) + (bytes ? p->an.c_lo_mn * es : 0);
   a.xmn = o + p->off_pos[0];
   a.xk = o + p->off_pos[1];
   a.yk = o + p->off_pos[2];
   a.ymn = o + p->off_pos[3];
   a.cm = o + p->off_pos[4];
   a.cn = o + p->off_pos[5];
-  a.xl = o + p->off_pos[6];
-  a.yl = o + p->off_pos[7];
-  a.cl = o + p->off_pos[8];
+  a.xl = lb + p->off_pos[6];
+  a.yl = lb + p->off_pos[7];
+  a.cl = lb + p->off_pos[8];
   a.M = (int32_t)p->an.M;
   a.N = (int32_t)p->an.N;
   a.K = (int32_t)p->an.K;
@@ -235,7 +262,7 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
     const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
     const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
-    st = p->index_bits == 32 ? upload<int32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
+    st = p->index_bits == 32 ? upload<uint32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
     if (st != FAMLIES_OK) {
       delete p;
       return st;
@@ -393,10 +420,10 @@ famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, cons
   L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
   hipError_t e;
   if (an.compute == FAMLIES_BF16X3 && L.kind == PlainLaunch::kMain) {
-    e = p->index_bits == 32 ? launch_bf16x3(make_args<int32_t>(p, x, y, C, alpha, beta), L, s)
+    e = p->index_bits == 32 ? launch_bf16x3(make_args<uint32_t>(p, x, y, C, alpha, beta), L, s)
                             : launch_bf16x3(make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
   } else {
-    e = p->index_bits == 32 ? launch_plain(an.dtype, make_args<int32_t>(p, x, y, C, alpha, beta), L, s)
+    e = p->index_bits == 32 ? launch_plain(an.dtype, make_args<uint32_t>(p, x, y, C, alpha, beta), L, s)
                             : launch_plain(an.dtype, make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");

@@ -5,9 +5,12 @@
 
 namespace famlies {
 
+// Offsets are either uint32_t byte offsets from the operand's lowest element
+// (when every operand spans less than 4 GiB) or int64_t element offsets from
+// the base pointer.
 template <typename OffT>
 struct PlainArgs {
-  const void* x;
+  const void* x;    // X, Y, C base pointers (the lowest element in the uint32_t form)
   const void* y;
   void* c;
   const OffT* xmn;  // X rows (M, padded)
@@ -16,9 +19,9 @@ struct PlainArgs {
   const OffT* ymn;  // Y columns (N, padded)
   const OffT* cm;   // C rows (M, padded)
   const OffT* cn;   // C columns (N, padded)
-  const OffT* xl;   // batch offsets of X, Y, C (L entries each)
-  const OffT* yl;
-  const OffT* cl;
+  const int64_t* xl;  // batch offsets of X, Y, C in elements (L entries each)
+  const int64_t* yl;
+  const int64_t* cl;
   int32_t M, N, K, L;
   int32_t tiles_m, tiles_n, splits, kchunk;
   double alpha, beta;

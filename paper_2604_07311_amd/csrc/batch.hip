@@ -33,7 +33,8 @@ namespace famlies {
 struct BatchProblemDev {
   int32_t M, N, K;
   int32_t flags;  // bit 0: swapped, bit 1: X gathered along K, bit 2: Y along K, bits 8..: tile class
-  int64_t off;    // first element of this problem's six indexing vectors in the pool
+  int64_t off;    // first entry of this problem's six indexing vectors in the pool
+  int64_t xlo, ylo, clo;  // element shift from each base pointer to the operand's lowest element
   int32_t pos[6]; // vector starts relative to off: X rows, X k, Y k, Y cols, C rows, C cols
 };
 
@@ -46,7 +47,7 @@ struct BatchArgs {
   const BatchProblemDev* probs;
   const BatchItem* items;
   const int32_t* wg_start;  // items of workgroup w: [wg_start[w], wg_start[w+1])
-  const int32_t* pool;      // indexing vectors
+  const uint32_t* pool;     // indexing vectors: byte offsets from each operand's lowest element
   const void* const* A;
   const void* const* B;
   void* const* C;
@@ -58,9 +59,9 @@ constexpr int kBatchClasses = 2;
 __host__ __device__ constexpr int batch_class_tile(int cls) { return cls == 0 ? 64 : 128; }
 
 template <typename T, int BT, bool XK, bool YK>
-__device__ __forceinline__ void run_item(const TileJob<int32_t>& j, T* smem) {
+__device__ __forceinline__ void run_item(const TileJob<uint32_t>& j, T* smem) {
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
-  PlainTile<T, BT, BT, BK, XK, YK>::template run<int32_t>(j, smem);
+  PlainTile<T, BT, BT, BK, XK, YK>::template run<uint32_t>(j, smem);
 }
 
 template <typename T>
@@ -77,11 +78,11 @@ __global__ __launch_bounds__(kThreads) void batch_contract(BatchArgs a) {
     const bool swapped = flags & 1;
     const int cls = flags >> 8;
     const int bt = cls == 0 ? 64 : 128;
-    const int32_t* o = a.pool + P.off;
-    TileJob<int32_t> j;
-    j.x = swapped ? a.B[item.prob] : a.A[item.prob];
-    j.y = swapped ? a.A[item.prob] : a.B[item.prob];
-    j.c = a.C[item.prob];
+    const uint32_t* o = a.pool + P.off;
+    TileJob<uint32_t> j;
+    j.x = static_cast<const T*>(swapped ? a.B[item.prob] : a.A[item.prob]) + P.xlo;
+    j.y = static_cast<const T*>(swapped ? a.A[item.prob] : a.B[item.prob]) + P.ylo;
+    j.c = static_cast<T*>(a.C[item.prob]) + P.clo;
     j.xmn = o + P.pos[0];
     j.xk = o + P.pos[1];
     j.yk = o + P.pos[2];
@@ -137,14 +138,14 @@ __global__ __launch_bounds__(kThreads) void batch_scale(BatchArgs a, const int32
   if ((int)blockIdx.x >= n) return;
   const int p = list ? list[blockIdx.x] : (int)blockIdx.x;
   const BatchProblemDev& P = a.probs[p];
-  const int32_t* o = a.pool + P.off;
-  T* C = static_cast<T*>(a.C[p]);
+  const uint32_t* o = a.pool + P.off;
+  T* C = static_cast<T*>(a.C[p]) + P.clo;
   const int64_t mn = (int64_t)P.M * P.N;
   const T be = static_cast<T>(a.beta);
   for (int64_t i = threadIdx.x; i < mn; i += kThreads) {
     const int m = (int)(i / P.N), nn = (int)(i % P.N);
-    const int32_t idx = o[P.pos[4] + m] + o[P.pos[5] + nn];
-    C[idx] = be != T(0) ? be * C[idx] : T(0);
+    T* cp = at(C, (uint32_t)(o[P.pos[4] + m] + o[P.pos[5] + nn]));
+    *cp = be != T(0) ? be * *cp : T(0);
   }
 }
 
@@ -176,7 +177,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   bp->dtype = dtype;
   bp->n = n;
   std::vector<BatchProblemDev> probs((size_t)n);
-  std::vector<int32_t> pool;
+  std::vector<uint32_t> pool;
   std::vector<int64_t> tmp;
   struct Job {
     int32_t prob;
@@ -198,9 +199,9 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
       delete bp;
       return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": batch modes in a batched plan");
     }
-    const int64_t lim = (int64_t)1 << 30;
-    if (an.max_abs_x >= lim || an.max_abs_y >= lim || an.max_abs_c >= lim || an.M >= lim || an.N >= lim ||
-        an.K >= lim) {
+    const int64_t lim = (int64_t)1 << 30, es = an.esize;
+    if ((an.x_span + 1) * es >= lim || (an.y_span + 1) * es >= lim || (an.c_span + 1) * es >= lim ||
+        an.M >= lim || an.N >= lim || an.K >= lim) {
       delete bp;
       return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": too large for the batched kernel");
     }
@@ -212,6 +213,9 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     d.K = (int32_t)an.K;
     d.flags = (an.swapped ? 1 : 0) | (an.x_kfast ? 2 : 0) | (an.y_kfast ? 4 : 0) | (cls << 8);
     d.off = (int64_t)pool.size();
+    d.xlo = an.x_lo;
+    d.ylo = an.y_lo;
+    d.clo = an.c_lo_mn;
     if (an.M == 0 || an.N == 0) continue;  // nothing to write
     const int64_t mp = cdiv(an.M, bt) * bt, np = cdiv(an.N, bt) * bt;
     const int64_t kp = cdiv(std::max<int64_t>(an.K, 1), BK) * BK + BK;
@@ -219,10 +223,11 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     const int which[6] = {0, 0, 1, 1, 2, 2};
     const int64_t len[6] = {an.M, an.K, an.K, an.N, an.M, an.N};
     const int64_t padded[6] = {mp, kp, kp, np, mp, np};
+    const int64_t shift[6] = {an.x_lo, 0, 0, an.y_lo, an.c_lo_mn, 0};
     for (int v = 0; v < 6; ++v) {
       d.pos[v] = (int32_t)(pool.size() - d.off);
       offsets(*groups[v], which[v], len[v], padded[v], tmp);
-      for (int64_t x : tmp) pool.push_back((int32_t)x);
+      for (int64_t x : tmp) pool.push_back((uint32_t)(uint64_t)((x - shift[v]) * es));  // byte offsets, mod 2^32
     }
     if (an.K == 0) {
       bp->scale_only.push_back((int)p);
@@ -294,7 +299,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   const size_t s_items = align(items.size() * sizeof(BatchItem) + 1);
   const size_t s_wg = align(wg_start.size() * sizeof(int32_t));
   const size_t s_scale = align(bp->scale_only.size() * sizeof(int32_t) + 1);
-  const size_t s_pool = align(pool.size() * sizeof(int32_t) + 1);
+  const size_t s_pool = align(pool.size() * sizeof(uint32_t) + 1);
   const size_t total = s_probs + s_items + s_wg + s_scale + s_pool;
   DeviceGuard dg(h->device);
   hipError_t e = hipMalloc(&bp->d_buf, total);
@@ -309,7 +314,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   std::memcpy(host.data() + s_probs + s_items, wg_start.data(), wg_start.size() * sizeof(int32_t));
   std::memcpy(host.data() + s_probs + s_items + s_wg, bp->scale_only.data(),
               bp->scale_only.size() * sizeof(int32_t));
-  std::memcpy(host.data() + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(int32_t));
+  std::memcpy(host.data() + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(uint32_t));
   e = hipMemcpy(bp->d_buf, host.data(), total, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     delete bp;
@@ -318,7 +323,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   bp->args.probs = reinterpret_cast<const BatchProblemDev*>(base);
   bp->args.items = reinterpret_cast<const BatchItem*>(base + s_probs);
   bp->args.wg_start = reinterpret_cast<const int32_t*>(base + s_probs + s_items);
-  bp->args.pool = reinterpret_cast<const int32_t*>(base + s_probs + s_items + s_wg + s_scale);
+  bp->args.pool = reinterpret_cast<const uint32_t*>(base + s_probs + s_items + s_wg + s_scale);
   bp->scale_dev = reinterpret_cast<const int32_t*>(base + s_probs + s_items + s_wg);
   auto* p = new (std::nothrow) famlies_plan_s();
   if (!p) {

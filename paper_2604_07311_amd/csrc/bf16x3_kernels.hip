@@ -36,7 +36,7 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo,
     const float x = gg.value(j, k0, kend);
     const __bf16 h = static_cast<__bf16>(x);
     const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
-    const int idx = KFAST ? (gg.r0 + j * G::RSTEP) * LDK + gg.kk0 : gg.r0 * LDK + gg.kk0 + j * G::KSTEP;
+    const int idx = gg.lds_index(j, LDK);
     hi[idx] = h;
     lo[idx] = l;
   }
@@ -173,10 +173,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
         for (int e = 0; e < 16; ++e) {
           const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
           if (m < a.M && n < a.N) {
-            const OffT idx = a.cm[m] + cn;
+            float* cp = at(C, (OffT)(a.cm[m] + cn));
             double v = a.alpha * ((double)hh[i][j][e] + (double)mid[i][j][e]);
-            if (a.beta != 0.0) v += a.beta * (double)C[idx];
-            C[idx] = (float)v;
+            if (a.beta != 0.0) v += a.beta * (double)*cp;
+            *cp = (float)v;
           }
         }
     }
@@ -206,11 +206,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_reduce(PlainArgs<OffT> a, int
   const size_t plane = (size_t)rows * ldw;
   double s = 0.0;
   for (int k = 0; k < a.splits; ++k) s += W[(size_t)k * plane + (size_t)m * ldw + n];
-  float* C = static_cast<float*>(a.c);
-  const OffT idx = a.cm[m] + a.cn[n];
+  float* cp = at(static_cast<float*>(a.c), (OffT)(a.cm[m] + a.cn[n]));
   double v = a.alpha * s;
-  if (a.beta != 0.0) v += a.beta * (double)C[idx];
-  C[idx] = (float)v;
+  if (a.beta != 0.0) v += a.beta * (double)*cp;
+  *cp = (float)v;
 }
 
 template <typename OffT, int BM, int BN>
@@ -241,7 +240,7 @@ static hipError_t launch_b3(const PlainArgs<OffT>& a, const PlainLaunch& L, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_bf16x3(const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s) {
+hipError_t launch_bf16x3(const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s) {
   return launch_b3(a, L, s);
 }
 hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {

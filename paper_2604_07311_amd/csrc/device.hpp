@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "args.hpp"
 
 namespace famlies {
@@ -29,6 +31,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
   int q = total / kXcds, r = total % kXcds;
   int xcd = bid % kXcds, idx = bid / kXcds;
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Element at `off` from `base`: uint32_t offsets count bytes (an SGPR base
+// plus a 32-bit VGPR offset per load), int64_t offsets count elements.
+template <typename T>
+__device__ __forceinline__ T* at(T* base, uint32_t off) {
+  typedef typename std::conditional<std::is_const<T>::value, const char, char>::type byte;
+  return reinterpret_cast<T*>(reinterpret_cast<byte*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ T* at(T* base, int64_t off) {
+  return base + off;
 }
 
 // MFMA shapes.  In every shape the lane index l selects the row (of the left
@@ -63,34 +77,39 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 
 // Gather of one operand tile (BR rows of the free dimension x BK contracted
 // indices) from strided global memory through the block-scatter indexing
-// vectors into LDS laid out [row][k] with leading dimension LDK.
+// vectors into LDS laid out [row][k] with leading dimension LDK (16-byte
+// aligned rows, padded by 16 bytes so that the MFMA operand reads and the
+// stores below are free of bank conflicts).
 //
 // KFAST (the operand's smallest stride is a contracted mode): lanes run along
-// k, each thread owns one k column and E rows.  Otherwise lanes run along the
-// rows, each thread owns one row and E k's; those k's are the same for a whole
-// wave when BR is a multiple of 64, so their offsets are wave-uniform.
+// k, each thread owns one k column and E rows.
+// Row-fast (otherwise): lanes run along the rows, each thread owns one row and
+// a run of E consecutive k's, stored to LDS as 16-byte vectors.  The k's are
+// the same for a whole wave when BR is a multiple of 64, so their offsets are
+// wave-uniform loads.
 // Rows past the problem edge carry offset 0 (a valid address) and only feed
 // accumulator rows that are never stored; k's past the edge are stored as 0.
 //
-// The three phases are split so a K loop can pipeline them: fetch_k() loads
-// the contracted-index offsets of a future slice, load() issues the data
-// loads of the next slice (no use of the loaded values, so nothing waits on
-// them until store()), store() writes the slice into LDS, zeroing k >= kend.
+// The phases are split so a K loop can pipeline them: fetch_k() loads the
+// contracted-index offsets of a future slice, load() issues the data loads of
+// the next slice (nothing waits on them until store()), store() writes the
+// slice into LDS, zeroing k >= kend.
 template <typename T, typename OffT, int BR, int BK, bool KFAST>
 struct TileGather {
   static constexpr int E = BR * BK / kThreads;
-  static constexpr int LDK = KFAST ? BK + 16 / (int)sizeof(T) : BK + 1;
-  static constexpr int RSTEP = kThreads / BK;  // KFAST: row step between a thread's elements
-  static constexpr int KSTEP = kThreads / BR;  // !KFAST: k step between a thread's elements
+  static constexpr int LDK = BK + 16 / (int)sizeof(T);
+  static constexpr int VK = 16 / (int)sizeof(T);  // k's per 16-byte vector
+  static constexpr int RSTEP = kThreads / BK;     // KFAST: row step between a thread's elements
+  static constexpr int KPH = kThreads / BR;       // row-fast: threads sharing one row
   static_assert(E >= 1, "tile too small for the workgroup");
   static_assert(KFAST ? (kThreads % BK == 0 && BR % RSTEP == 0)
-                      : (kThreads % BR == 0 && BK % KSTEP == 0),
+                      : (kThreads % BR == 0 && BK % KPH == 0 && E % VK == 0),
                 "tile shape does not divide the workgroup");
 
   OffT mn[KFAST ? E : 1];  // row offsets, fixed for the tile
   OffT ko[KFAST ? 1 : E];  // contracted-index offsets of the slice to load next
   T v[E];
-  int r0, kk0;
+  int r0, kk0;             // KFAST: kk0 = the thread's k; row-fast: first of its E k's
 
   __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
     if constexpr (KFAST) {
@@ -100,7 +119,7 @@ struct TileGather {
       for (int j = 0; j < E; ++j) mn[j] = mnoff[tile_r0 + r0 + j * RSTEP];
     } else {
       r0 = tid % BR;
-      kk0 = tid / BR;
+      kk0 = (tid / BR) * E;
       if constexpr (BR % 64 == 0) kk0 = __builtin_amdgcn_readfirstlane(kk0);
       mn[0] = mnoff[tile_r0 + r0];
     }
@@ -112,33 +131,44 @@ struct TileGather {
       ko[0] = koff[k0 + kk0];
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) ko[j] = koff[k0 + kk0 + j * KSTEP];
+      for (int j = 0; j < E; ++j) ko[j] = koff[k0 + kk0 + j];
     }
   }
 
   __device__ __forceinline__ void load(const T* __restrict__ base) {
     if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = base[mn[j] + ko[0]];
+      for (int j = 0; j < E; ++j) v[j] = *at(base, (OffT)(mn[j] + ko[0]));
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = base[mn[0] + ko[j]];
+      for (int j = 0; j < E; ++j) v[j] = *at(base, (OffT)(mn[0] + ko[j]));
     }
   }
 
   // Value of element j of the slice starting at k0 (0 past kend).
   __device__ __forceinline__ T value(int j, int k0, int kend) const {
-    const int k = KFAST ? k0 + kk0 : k0 + kk0 + j * KSTEP;
+    const int k = KFAST ? k0 + kk0 : k0 + kk0 + j;
     return k < kend ? v[j] : T(0);
   }
 
-  __device__ __forceinline__ int lds_index(int j) const {
-    return KFAST ? (r0 + j * RSTEP) * LDK + kk0 : r0 * LDK + kk0 + j * KSTEP;
+  __device__ __forceinline__ int lds_index(int j, int ldk) const {
+    return KFAST ? (r0 + j * RSTEP) * ldk + kk0 : r0 * ldk + kk0 + j;
   }
 
   __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
+    if constexpr (KFAST) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) lds[lds_index(j)] = value(j, k0, kend);
+      for (int j = 0; j < E; ++j) lds[(r0 + j * RSTEP) * LDK + kk0] = value(j, k0, kend);
+    } else {
+      typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+#pragma unroll
+      for (int q = 0; q < E / VK; ++q) {
+        vec_t w;
+#pragma unroll
+        for (int u = 0; u < VK; ++u) w[u] = value(q * VK + u, k0, kend);
+        *reinterpret_cast<vec_t*>(lds + r0 * LDK + kk0 + q * VK) = w;
+      }
+    }
   }
 };
 

@@ -42,6 +42,11 @@ struct Analysis {
   // tensors A, B, C: [lo, hi]; empty tensors have lo > hi.
   int64_t a_lo = 0, a_hi = -1, b_lo = 0, b_hi = -1, c_lo = 0, c_hi = -1;
   int64_t max_abs_x = 0, max_abs_y = 0, max_abs_c = 0;  // bounds on |offset sums|
+  // Lowest element offset (<= 0) and reach (max - min offset) of each kernel
+  // operand over its non-batch modes: X over I and P, Y over J and P, C over
+  // I and J.  Offsets rebased by the lowest one are non-negative.
+  int64_t x_lo = 0, y_lo = 0, c_lo_mn = 0;
+  int64_t x_span = 0, y_span = 0, c_span = 0;
   int n_trace = 0, n_diag = 0;  // labels summed inside one input / repeated in an input
   int esize = 8;
 };

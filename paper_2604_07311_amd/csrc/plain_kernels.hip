@@ -68,12 +68,11 @@ __global__ __launch_bounds__(kThreads) void splitk_reduce(PlainArgs<OffT> a, int
   const size_t plane = (size_t)rows * ldw;
   T s = T(0);
   for (int k = 0; k < a.splits; ++k) s += W[(size_t)k * plane + (size_t)m * ldw + n];
-  T* C = static_cast<T*>(a.c);
-  const OffT idx = a.cm[m] + a.cn[n];
+  T* cp = at(static_cast<T*>(a.c), (OffT)(a.cm[m] + a.cn[n]));
   const T al = static_cast<T>(a.alpha), be = static_cast<T>(a.beta);
   T v = al * s;
-  if (be != T(0)) v += be * C[idx];
-  C[idx] = v;
+  if (be != T(0)) v += be * *cp;
+  *cp = v;
 }
 
 // K == 0 or alpha == 0: C = beta * C (beta == 0 writes zeros without reading C).
@@ -85,10 +84,9 @@ __global__ __launch_bounds__(kThreads) void scale_c(PlainArgs<OffT> a) {
   const int l = (int)(i / mn);
   const int64_t r = i % mn;
   const int m = (int)(r / a.N), n = (int)(r % a.N);
-  T* C = static_cast<T*>(a.c);
-  const OffT idx = a.cl[l] + a.cm[m] + a.cn[n];
+  T* cp = at(static_cast<T*>(a.c) + a.cl[l], (OffT)(a.cm[m] + a.cn[n]));
   const T be = static_cast<T>(a.beta);
-  C[idx] = be != T(0) ? be * C[idx] : T(0);
+  *cp = be != T(0) ? be * *cp : T(0);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -127,9 +125,9 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   return hipGetLastError();
 }
 
-hipError_t launch_plain(int dtype, const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s) {
-  return dtype == FAMLIES_F64 ? launch_plain_t<double, int32_t>(a, L, s)
-                              : launch_plain_t<float, int32_t>(a, L, s);
+hipError_t launch_plain(int dtype, const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s) {
+  return dtype == FAMLIES_F64 ? launch_plain_t<double, uint32_t>(a, L, s)
+                              : launch_plain_t<float, uint32_t>(a, L, s);
 }
 
 hipError_t launch_plain(int dtype, const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {

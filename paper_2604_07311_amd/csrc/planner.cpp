@@ -115,6 +115,16 @@ int64_t reach(const std::vector<Mode>& g, int which) {
   return r;
 }
 
+// Sum over the modes of the most negative offset each can contribute.
+int64_t lowest(const std::vector<Mode>& g, int which) {
+  int64_t r = 0;
+  for (const Mode& md : g) {
+    const int64_t t = (md.ext - 1) * sel(md, which);
+    if (t < 0) r += t;
+  }
+  return r;
+}
+
 }  // namespace
 
 int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tensor* B,
@@ -260,6 +270,12 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   an.max_abs_x = reach(an.I, 0) + reach(an.P, 0) + reach(an.Lm, 0);
   an.max_abs_y = reach(an.J, 1) + reach(an.P, 1) + reach(an.Lm, 1);
   an.max_abs_c = reach(an.I, 2) + reach(an.J, 2) + reach(an.Lm, 2);
+  an.x_lo = lowest(an.I, 0) + lowest(an.P, 0);
+  an.y_lo = lowest(an.J, 1) + lowest(an.P, 1);
+  an.c_lo_mn = lowest(an.I, 2) + lowest(an.J, 2);
+  an.x_span = reach(an.I, 0) + reach(an.P, 0);
+  an.y_span = reach(an.J, 1) + reach(an.P, 1);
+  an.c_span = reach(an.I, 2) + reach(an.J, 2);
   *out = an;
   return FAMLIES_OK;
 }

@@ -50,7 +50,8 @@ struct famlies_plan_s {
   famlies::TileCfg cfg;
   int index_bits = 32;
   int kchunk = 0;
-  void* d_off = nullptr;   // nine indexing vectors, back to back
+  void* d_off = nullptr;   // six OffT indexing vectors, then three int64 batch vectors
+  size_t batch_off_bytes = 0;
   size_t off_pos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   void* d_work = nullptr;  // split-K partial sums
   size_t work_bytes = 0;
@@ -78,7 +79,7 @@ famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, i
                          const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
                          const TileCfg* force);
 
-hipError_t launch_bf16x3(const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s);
+hipError_t launch_bf16x3(const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s);
 hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s);
 bool bf16x3_tile_supported(int bm, int bn);
 

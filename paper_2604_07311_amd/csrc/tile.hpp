@@ -35,8 +35,8 @@ struct PlainTile {
   using GX = TileGather<T, OffT, BM, BK, XK>;
   template <typename OffT>
   using GY = TileGather<T, OffT, BN, BK, YK>;
-  static constexpr int LX = XK ? BK + 16 / (int)sizeof(T) : BK + 1;
-  static constexpr int LY = YK ? BK + 16 / (int)sizeof(T) : BK + 1;
+  static constexpr int LX = GX<int32_t>::LDK;
+  static constexpr int LY = GY<int32_t>::LDK;
   static constexpr int XS = BM * LX, YS = BN * LY;
   static constexpr int SMEM = 2 * (XS + YS);  // elements of T
   static constexpr int WTM = BM / 2, WTN = BN / 2;
@@ -126,10 +126,10 @@ struct PlainTile {
           for (int e = 0; e < MF::NACC; ++e) {
             const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
             if (m < j.M && n < j.N) {
-              const OffT idx = j.cm[m] + cn;
+              T* cp = at(C, (OffT)(j.cm[m] + cn));
               T v = al * acc[i][jj][e];
-              if (be != T(0)) v += be * C[idx];
-              C[idx] = v;
+              if (be != T(0)) v += be * *cp;
+              *cp = v;
             }
           }
         }
