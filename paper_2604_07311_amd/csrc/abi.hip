@@ -246,6 +246,12 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   p->cfg = force ? *force : choose_tiles(h, an);
   if (compute == FAMLIES_BF16X3) {
     p->cfg.bk = 32;
+    // large problems: a 256 x 128 tile (128 x 64 per wave) halves the LDS
+    // bytes per MFMA that the 128 x 128 tile needs
+    if (!force && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1) {
+      p->cfg.bm = 256;
+      p->cfg.bn = 128;
+    }
     if (!bf16x3_tile_supported(p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
   } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
     p->cfg.bm = p->cfg.bn = 128;

@@ -21,50 +21,65 @@ __device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-template <bool KFAST, int BK>
-struct SplitLds {
-  // bf16 row pitch: K-gathered tiles keep 16-byte aligned rows (+8 bf16),
-  // row-gathered tiles use an odd dword pitch (+2 bf16) so that lanes writing
-  // consecutive rows hit different banks.
-  static constexpr int LDK = KFAST ? BK + 8 : BK + 2;
-};
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-template <typename G, bool KFAST, int LDK>
+// Split two floats into packed bf16 pairs hi (RNE of x) and lo (RNE of
+// x - hi; the difference is exact in FP32).
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t* hi, uint32_t* lo) {
+  const f32x2 x = {x0, x1};
+  const bf16x2 h = __builtin_convertvector(x, bf16x2);
+  const f32x2 r = x - __builtin_convertvector(h, f32x2);
+  const bf16x2 l = __builtin_convertvector(r, bf16x2);
+  *hi = __builtin_bit_cast(uint32_t, h);
+  *lo = __builtin_bit_cast(uint32_t, l);
+}
+
+// bf16 LDS tiles: [row][k] with 16-byte aligned rows of BK + 8 entries.
+constexpr int kB3K = 32;            // contraction slice per stage
+constexpr int kB3LD = kB3K + 8;     // row pitch in bf16
+
+// Write the split of a gathered slice into the hi and lo tiles.  K-gathered
+// threads own pairs of consecutive k's (one packed dword per row and part);
+// row-gathered threads own a run of k's in one row (8-byte stores).
+template <typename G, bool KFAST>
 __device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo, int k0, int kend) {
+  if constexpr (KFAST) {
+    static_assert(G::KVT == 2, "K-gathered bf16 split stores pairs of k");
 #pragma unroll
-  for (int j = 0; j < G::E; ++j) {
-    const float x = gg.value(j, k0, kend);
-    const __bf16 h = static_cast<__bf16>(x);
-    const __bf16 l = static_cast<__bf16>(x - static_cast<float>(h));
-    const int idx = gg.lds_index(j, LDK);
-    hi[idx] = h;
-    lo[idx] = l;
-  }
-}
-
-// 8 consecutive bf16 starting at p (4-byte aligned at least).
-template <bool ALIGN16>
-__device__ __forceinline__ bf16x8 read8(const __bf16* p) {
-  if constexpr (ALIGN16) {
-    return *reinterpret_cast<const bf16x8*>(p);
+    for (int i = 0; i < G::E / 2; ++i) {
+      uint32_t h, l;
+      split2(gg.value(2 * i, k0, kend), gg.value(2 * i + 1, k0, kend), &h, &l);
+      const int idx = gg.lds_index(2 * i, kB3LD);
+      *reinterpret_cast<uint32_t*>(hi + idx) = h;
+      *reinterpret_cast<uint32_t*>(lo + idx) = l;
+    }
   } else {
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-    u32x4 w = {q[0], q[1], q[2], q[3]};
-    return __builtin_bit_cast(bf16x8, w);
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int q = 0; q < G::E / 4; ++q) {
+      uint32_t h0, l0, h1, l1;
+      split2(gg.value(4 * q, k0, kend), gg.value(4 * q + 1, k0, kend), &h0, &l0);
+      split2(gg.value(4 * q + 2, k0, kend), gg.value(4 * q + 3, k0, kend), &h1, &l1);
+      const u32x2 h = {h0, h1}, l = {l0, l1};
+      const int idx = gg.lds_index(4 * q, kB3LD);
+      *reinterpret_cast<u32x2*>(hi + idx) = h;
+      *reinterpret_cast<u32x2*>(lo + idx) = l;
+    }
   }
 }
 
+// One workgroup: a BM x BN tile of C, 2 x 2 waves of (BM/2) x (BN/2), each
+// made of 32 x 32 MFMA blocks.
 template <typename OffT, int BM, int BN, bool XK, bool YK>
 __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
-  constexpr int BK = 32;
-  using GX = TileGather<float, OffT, BM, BK, XK>;
-  using GY = TileGather<float, OffT, BN, BK, YK>;
-  constexpr int LX = SplitLds<XK, BK>::LDK, LY = SplitLds<YK, BK>::LDK;
+  constexpr int BK = kB3K;
+  using GX = TileGather<float, OffT, BM, BK, XK, XK ? 2 : 1>;
+  using GY = TileGather<float, OffT, BN, BK, YK, YK ? 2 : 1>;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
-  constexpr int XS = BM * LX, YS = BN * LY;      // bf16 elements per tile
-  constexpr int STAGE = 2 * XS + 2 * YS;         // hi and lo of both tiles
+  constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per tile
+  constexpr int STAGE = 2 * XS + 2 * YS;           // hi and lo of both tiles
   __shared__ __attribute__((aligned(16))) __bf16 smem[2 * STAGE];
 
   const int tid = threadIdx.x;
@@ -102,8 +117,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
   const int g = lane / 32, r = lane % 32;
   auto stage_store = [&](int buf, int k0) {
     __bf16* base = smem + buf * STAGE;
-    store_split<GX, XK, LX>(gx, base, base + XS, k0, kend);
-    store_split<GY, YK, LY>(gy, base + 2 * XS, base + 2 * XS + YS, k0, kend);
+    store_split<GX, XK>(gx, base, base + XS, k0, kend);
+    store_split<GY, YK>(gy, base + 2 * XS, base + 2 * XS + YS, k0, kend);
   };
   if (nk > 0) {
     gx.fetch_k(a.xk, kbeg);
@@ -137,15 +152,15 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
         bf16x8 ah[MB], al[MB], bh[NB], bl[NB];
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-          const int o = (wm * WTM + i * 32 + r) * LX + g * 16 + s * 8;
-          ah[i] = read8<XK>(xh + o);
-          al[i] = read8<XK>(xl + o);
+          const int o = (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8;
+          ah[i] = *reinterpret_cast<const bf16x8*>(xh + o);
+          al[i] = *reinterpret_cast<const bf16x8*>(xl + o);
         }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-          const int o = (wn * WTN + j * 32 + r) * LY + g * 16 + s * 8;
-          bh[j] = read8<YK>(yh + o);
-          bl[j] = read8<YK>(yl + o);
+          const int o = (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8;
+          bh[j] = *reinterpret_cast<const bf16x8*>(yh + o);
+          bl[j] = *reinterpret_cast<const bf16x8*>(yl + o);
         }
 #pragma unroll
         for (int i = 0; i < MB; ++i)
@@ -229,7 +244,9 @@ template <typename OffT>
 static hipError_t launch_b3(const PlainArgs<OffT>& a, const PlainLaunch& L, hipStream_t s) {
   const int grid = a.tiles_m * a.tiles_n * a.splits * a.L;
   hipError_t e = hipErrorInvalidValue;
-  if (L.bm == 128 && L.bn == 128)
+  if (L.bm == 256 && L.bn == 128)
+    e = launch_b3_tile<OffT, 256, 128>(a, L.xk, L.yk, grid, s);
+  else if (L.bm == 128 && L.bn == 128)
     e = launch_b3_tile<OffT, 128, 128>(a, L.xk, L.yk, grid, s);
   else if (L.bm == 64 && L.bn == 64)
     e = launch_b3_tile<OffT, 64, 64>(a, L.xk, L.yk, grid, s);
@@ -246,6 +263,8 @@ hipError_t launch_bf16x3(const PlainArgs<uint32_t>& a, const PlainLaunch& L, hip
 hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {
   return launch_b3(a, L, s);
 }
-bool bf16x3_tile_supported(int bm, int bn) { return (bm == 128 && bn == 128) || (bm == 64 && bn == 64); }
+bool bf16x3_tile_supported(int bm, int bn) {
+  return (bm == 256 && bn == 128) || (bm == 128 && bn == 128) || (bm == 64 && bn == 64);
+}
 
 }  // namespace famlies

@@ -82,7 +82,8 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 // stores below are free of bank conflicts).
 //
 // KFAST (the operand's smallest stride is a contracted mode): lanes run along
-// k, each thread owns one k column and E rows.
+// k; each thread owns KV consecutive k's (KV = 1 for the plain kernels, 2 for
+// the bf16 split, whose stores pack pairs) in E / KV rows.
 // Row-fast (otherwise): lanes run along the rows, each thread owns one row and
 // a run of E consecutive k's, stored to LDS as 16-byte vectors.  The k's are
 // the same for a whole wave when BR is a multiple of 64, so their offsets are
@@ -93,30 +94,33 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 // The phases are split so a K loop can pipeline them: fetch_k() loads the
 // contracted-index offsets of a future slice, load() issues the data loads of
 // the next slice (nothing waits on them until store()), store() writes the
-// slice into LDS, zeroing k >= kend.
-template <typename T, typename OffT, int BR, int BK, bool KFAST>
+// slice into LDS, zeroing k >= kend.  Element j of a thread is
+// (row j / KV, k j % KV) in the KFAST case and (row 0, k j) otherwise.
+template <typename T, typename OffT, int BR, int BK, bool KFAST, int KV = 1>
 struct TileGather {
   static constexpr int E = BR * BK / kThreads;
+  static constexpr int KVT = KV;                  // KFAST: consecutive k's per thread
   static constexpr int LDK = BK + 16 / (int)sizeof(T);
   static constexpr int VK = 16 / (int)sizeof(T);  // k's per 16-byte vector
-  static constexpr int RSTEP = kThreads / BK;     // KFAST: row step between a thread's elements
+  static constexpr int KT = BK / KV;              // KFAST: threads along k
+  static constexpr int RSTEP = kThreads / KT;     // KFAST: row step between a thread's rows
   static constexpr int KPH = kThreads / BR;       // row-fast: threads sharing one row
-  static_assert(E >= 1, "tile too small for the workgroup");
-  static_assert(KFAST ? (kThreads % BK == 0 && BR % RSTEP == 0)
+  static_assert(E >= 1 && E % KV == 0, "tile too small for the workgroup");
+  static_assert(KFAST ? (kThreads % KT == 0 && BR % RSTEP == 0)
                       : (kThreads % BR == 0 && BK % KPH == 0 && E % VK == 0),
                 "tile shape does not divide the workgroup");
 
-  OffT mn[KFAST ? E : 1];  // row offsets, fixed for the tile
-  OffT ko[KFAST ? 1 : E];  // contracted-index offsets of the slice to load next
+  OffT mn[KFAST ? E / KV : 1];  // row offsets, fixed for the tile
+  OffT ko[KFAST ? KV : E];      // contracted-index offsets of the slice to load next
   T v[E];
-  int r0, kk0;             // KFAST: kk0 = the thread's k; row-fast: first of its E k's
+  int r0, kk0;  // first row; first k of the thread's run
 
   __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
     if constexpr (KFAST) {
-      kk0 = tid % BK;
-      r0 = tid / BK;
+      kk0 = (tid % KT) * KV;
+      r0 = tid / KT;
 #pragma unroll
-      for (int j = 0; j < E; ++j) mn[j] = mnoff[tile_r0 + r0 + j * RSTEP];
+      for (int i = 0; i < E / KV; ++i) mn[i] = mnoff[tile_r0 + r0 + i * RSTEP];
     } else {
       r0 = tid % BR;
       kk0 = (tid / BR) * E;
@@ -127,38 +131,31 @@ struct TileGather {
 
   // Offsets of slice [k0, k0 + BK); koff must hold k0 + BK entries.
   __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
-    if constexpr (KFAST) {
-      ko[0] = koff[k0 + kk0];
-    } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) ko[j] = koff[k0 + kk0 + j];
-    }
+    for (int u = 0; u < (KFAST ? KV : E); ++u) ko[u] = koff[k0 + kk0 + u];
   }
 
   __device__ __forceinline__ void load(const T* __restrict__ base) {
-    if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = *at(base, (OffT)(mn[j] + ko[0]));
-    } else {
-#pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = *at(base, (OffT)(mn[0] + ko[j]));
-    }
+    for (int j = 0; j < E; ++j)
+      v[j] = KFAST ? *at(base, (OffT)(mn[j / KV] + ko[j % KV])) : *at(base, (OffT)(mn[0] + ko[j]));
   }
+
+  __device__ __forceinline__ int krel(int j) const { return kk0 + (KFAST ? j % KV : j); }
 
   // Value of element j of the slice starting at k0 (0 past kend).
   __device__ __forceinline__ T value(int j, int k0, int kend) const {
-    const int k = KFAST ? k0 + kk0 : k0 + kk0 + j;
-    return k < kend ? v[j] : T(0);
+    return k0 + krel(j) < kend ? v[j] : T(0);
   }
 
   __device__ __forceinline__ int lds_index(int j, int ldk) const {
-    return KFAST ? (r0 + j * RSTEP) * ldk + kk0 : r0 * ldk + kk0 + j;
+    return KFAST ? (r0 + (j / KV) * RSTEP) * ldk + kk0 + j % KV : r0 * ldk + kk0 + j;
   }
 
   __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
     if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) lds[(r0 + j * RSTEP) * LDK + kk0] = value(j, k0, kend);
+      for (int j = 0; j < E; ++j) lds[lds_index(j, LDK)] = value(j, k0, kend);
     } else {
       typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
 #pragma unroll
