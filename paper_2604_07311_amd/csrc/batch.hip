@@ -65,7 +65,7 @@ __device__ __forceinline__ void run_item(const TileJob<uint32_t>& j, T* smem) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void batch_contract(BatchArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
   constexpr int SM = PlainTile<T, 128, 128, BK, true, true>::SMEM;
   __shared__ T smem[SM];
@@ -249,8 +249,17 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     delete bp;
     return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: indexing vectors exceed 2^31 entries");
   }
-  // Grid: two workgroups per CU (the kernel's LDS and register budget).
-  const int grid = std::max(8, 2 * h->num_cus);
+  // Grid: as many workgroups as can be resident at once (every one of them
+  // runs its whole item list, so none may wait for another to finish).
+  int per_cu = 0;
+  {
+    DeviceGuard dg0(h->device);
+    hipError_t oe = dtype == FAMLIES_F64
+                        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_contract<double>, kThreads, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_contract<float>, kThreads, 0);
+    if (oe != hipSuccess || per_cu < 1) per_cu = 1;
+  }
+  const int grid = std::max(8, (per_cu * h->num_cus) / 8 * 8);
   const int per_xcd = grid / 8;
   // 1) problems -> XCDs, largest first, to the least-loaded XCD
   std::vector<int64_t> order((size_t)n);
