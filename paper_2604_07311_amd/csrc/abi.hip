@@ -64,9 +64,14 @@ DeviceGuard::~DeviceGuard() {
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Step a4: tile shape and split-K.  A tile-table entry for the problem's
-// size class wins; otherwise large tiles for large problems, small tiles when
-// the large ones would leave most CUs idle, and split-K when even that does
-// not fill the chip and K is long.
+// size class wins.  Otherwise a small cost model picks the tile edge (128 or
+// 64) and the number of K slices: the workgroups are dealt to the CUs two at
+// a time (two share a CU at half rate each; a lone one runs at about 0.65 of
+// the CU), so the busiest CU's time is
+//     pairs * 2w + (odd ? w / 0.65 : 0),  w = work of one workgroup,
+// a 64-edge tile does its flops at about 0.75 of the 128-edge rate, and each
+// extra K slice costs a pass over M*N partial sums (at HBM rate, measured in
+// the same units).  The model only ranks candidates; it is not a timing.
 TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
   TileCfg t;
   const int bk = an.dtype == FAMLIES_F64 ? 16 : 32;
@@ -74,20 +79,30 @@ TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
   if (an.M == 0 || an.N == 0 || an.K == 0) return t;
   if (h && h->table.lookup_plain(an, &t)) return t;
   const int cus = h ? h->num_cus : 256;
-  const int64_t big = ceil_div(an.M, 128) * ceil_div(an.N, 128) * an.L;
-  if (big >= cus / 2) {
-    t.bm = t.bn = 128;
-  } else {
-    t.bm = t.bn = 64;
+  // CU throughput in flop/s and HBM bandwidth in bytes/s (MI355X-class)
+  const double cu_rate = (an.dtype == FAMLIES_F64 ? 78.6e12 : 157.3e12) / 256.0;
+  const double hbm = 8.0e12 * cus / 256.0;
+  const double es = an.esize;
+  double best = 1e300;
+  TileCfg pick = t;
+  for (int bt : {128, 64}) {
+    const int64_t tiles = ceil_div(an.M, bt) * ceil_div(an.N, bt) * an.L;
+    const double eff = bt == 128 ? 1.0 : 0.75;
+    for (int split : {1, 2, 3, 4, 6, 8, 12, 16}) {
+      if (split > 1 && (an.L > 1 || an.K / split < 2 * bk)) continue;
+      const int64_t units = tiles * split;
+      const int64_t q = ceil_div(units, cus);  // workgroups on the busiest CU
+      const double w = 2.0 * bt * bt * ((double)an.K / split) / (cu_rate * eff);
+      double time = (double)(q / 2) * 2.0 * w + (q % 2 ? w / 0.65 : 0.0);
+      if (split > 1) time += (double)split * an.M * an.N * es * 2.0 / hbm + 4e-6;
+      if (time < best * 0.9) {  // prefer fewer slices / larger tiles unless clearly faster
+        best = time;
+        pick.bm = pick.bn = bt;
+        pick.split = split;
+      }
+    }
   }
-  const int64_t tiles = ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn) * an.L;
-  t.split = 1;
-  if (tiles < cus && an.L == 1) {
-    int64_t want = ceil_div(2 * cus, tiles);
-    int64_t maxs = std::max<int64_t>(1, an.K / (2 * bk));
-    t.split = (int)std::max<int64_t>(1, std::min<int64_t>({want, maxs, 64}));
-  }
-  return t;
+  return pick;
 }
 
 static void finalize_split(TileCfg* t, int64_t K, int* kchunk) {
