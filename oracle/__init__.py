@@ -127,12 +127,13 @@ def contract(alpha: float,
              b: Tuple[np.ndarray, int, Sequence[int], Sequence[int]], lb,
              beta: float,
              c: Tuple[np.ndarray, int, Sequence[int], Sequence[int]], lc,
-             *, split: bool = False, compensated: bool = True,
+             *, split=False, compensated: bool = True,
              want_cond: bool = False, nthreads: Optional[int] = None,
              lib: Optional[ctypes.CDLL] = None):
     """Return a new storage array holding C = alpha*A.B + beta*C0 (C0 = c's
     buffer, which is not modified), and the condition tensor D (same storage
-    layout) when ``want_cond``."""
+    layout) when ``want_cond``.  ``split``: False / 0 exact products, True / 1
+    the bf16x3 split, 2 the bf16x6 split (see oracle.c)."""
     lib = lib or load()
     abuf, abase, aext, astr = a
     bbuf, bbase, bext, bstr = b
@@ -146,14 +147,14 @@ def contract(alpha: float,
                              ctypes.byref(tb), _base_ptr(bbuf, bbase), float(beta),
                              ctypes.byref(tc), _base_ptr(out, cbase),
                              _base_ptr(d, cbase) if want_cond else None,
-                             int(bool(split)), int(bool(compensated)), _threads(nthreads))
+                             int(split), int(bool(compensated)), _threads(nthreads))
     if rc != OK:
         raise OracleError(rc)
     return (out, d) if want_cond else out
 
 
 def contract_entries(alpha: float, a, la, b, lb, beta: float, c, lc,
-                     cidx: np.ndarray, *, split: bool = False, compensated: bool = True,
+                     cidx: np.ndarray, *, split=False, compensated: bool = True,
                      want_cond: bool = False, nthreads: Optional[int] = None,
                      lib: Optional[ctypes.CDLL] = None):
     """Compute only the C entries whose multi-indices are the rows of
@@ -175,7 +176,7 @@ def contract_entries(alpha: float, a, la, b, lb, beta: float, c, lc,
         idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
         d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if want_cond else None,
-        int(bool(split)), int(bool(compensated)), _threads(nthreads))
+        int(split), int(bool(compensated)), _threads(nthreads))
     if rc != OK:
         raise OracleError(rc)
     return (out, d) if want_cond else out

@@ -21,8 +21,7 @@
  * base + sum_d index(label_d) * stride_d.  These are einsum semantics: a label
  * in all three tensors acts as a batch index, a label only in A (or only in
  * B) is summed inside the product, and a label repeated within A or B selects
- * a diagonal.  The library implements the classical case (every label in
- * exactly two tensors); the wider semantics here pin later extensions.
+ * a diagonal.
  *
  * Conventions (the paper is silent; readings listed with the design notes):
  *   - beta == 0: C is not read (BLAS convention), so NaN in C0 does not leak.
@@ -37,6 +36,10 @@
  *     new and mixed precisions"): hi = RNE_bf16(x), lo = RNE_bf16(x - hi),
  *     product = hi_a*hi_b + hi_a*lo_b + lo_a*hi_b, each term exact in FP64.
  *     This is the split-exact reference for the bf16x3 path.
+ *   - split == 2 splits each operand three ways, h = RNE_bf16(x),
+ *     m = RNE_bf16(x - h), l = RNE_bf16(x - h - m) (the differences are exact
+ *     in FP32), and keeps the six products whose orders sum to at most two
+ *     units of 2^-8: hh, hm, mh, hl, lh, mm.  Reference for the bf16x6 path.
  *
  * Built with -O2 -fopenmp -ffp-contract=off and no fast-math, so results are
  * reproducible on any x86-64 host.
@@ -193,12 +196,24 @@ static void one_entry(const problem *p, int64_t *idx, const double *a, const dou
     }
     double x = a[offA], y = b[offB];
     acc.abssum += fabs(x * y);
-    if (split) {
+    if (split == 1) {
       float xf = (float)x, yf = (float)y;
       float xh = bf16_rne(xf), yh = bf16_rne(yf);
       float xl = bf16_rne(xf - xh), yl = bf16_rne(yf - yh);
       acc_add(&acc, (double)xh * (double)yh, compensated);
       acc_add(&acc, (double)xh * (double)yl, compensated);
+      acc_add(&acc, (double)xl * (double)yh, compensated);
+    } else if (split == 2) {
+      float xf = (float)x, yf = (float)y;
+      float xh = bf16_rne(xf), yh = bf16_rne(yf);
+      float xr = xf - xh, yr = yf - yh;
+      float xm = bf16_rne(xr), ym = bf16_rne(yr);
+      float xl = bf16_rne(xr - xm), yl = bf16_rne(yr - ym);
+      acc_add(&acc, (double)xh * (double)yh, compensated);
+      acc_add(&acc, (double)xh * (double)ym, compensated);
+      acc_add(&acc, (double)xm * (double)yh, compensated);
+      acc_add(&acc, (double)xh * (double)yl, compensated);
+      acc_add(&acc, (double)xm * (double)ym, compensated);
       acc_add(&acc, (double)xl * (double)yh, compensated);
     } else {
       acc_add(&acc, x * y, compensated);

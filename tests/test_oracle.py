@@ -362,6 +362,50 @@ def test_split_exact_when_inputs_are_bf16(oracle_lib):
     np.testing.assert_array_equal(s, x)
 
 
+def _split6_ref_numpy(p):
+    """The bf16x6 split with torch's bf16 rounding and numpy einsum in FP64:
+    hh + hm + mh + hl + mm + lh."""
+    torch = pytest.importorskip("torch")
+
+    def split(buf):
+        x = torch.from_numpy(buf.astype(np.float32))
+        h = x.to(torch.bfloat16).to(torch.float32)
+        r = x - h
+        m = r.to(torch.bfloat16).to(torch.float32)
+        l = (r - m).to(torch.bfloat16).to(torch.float32)
+        return [t.numpy().astype(np.float64) for t in (h, m, l)]
+
+    a = [_as_dense(t, p.a) for t in split(p.abuf)]
+    b = [_as_dense(t, p.b) for t in split(p.bbuf)]
+    ein = "%s,%s->%s" % (p.la, p.lb, p.lc)
+    return sum(np.einsum(ein, a[i], b[j]) for i in range(3) for j in range(3) if i + j <= 2)
+
+
+def test_bf16x6_split_matches_library_split(oracle_lib):
+    p = synth.plain16(seed=41, n=5, dist="outliers")
+    p.abuf = p.abuf.astype(np.float32).astype(np.float64)
+    p.bbuf = p.bbuf.astype(np.float32).astype(np.float64)
+    out, d = oracle.contract(1.0, *p.oracle_args()[:4], 0.0, *p.oracle_args()[4:],
+                             split=2, want_cond=True)
+    want = _split6_ref_numpy(p)
+    assert np.all(np.abs(_as_dense(out, p.c) - want) <= 2 * 6 * 25 * 2.0 ** -53 * _as_dense(d, p.c))
+
+
+def test_bf16x6_error_bound(oracle_lib):
+    """Dropping m*l, l*m and l*l costs at most about 2^-23 |a||b| per product;
+    the bf16x6 result is within 2^-22 D of the exact one and far closer than
+    bf16x3."""
+    p = synth.plain16(seed=42, n=6)
+    p.abuf = p.abuf.astype(np.float32).astype(np.float64)
+    p.bbuf = p.bbuf.astype(np.float32).astype(np.float64)
+    args = (1.0, *p.oracle_args()[:4], 0.0, *p.oracle_args()[4:])
+    exact, d = oracle.contract(*args, want_cond=True)
+    s6 = oracle.contract(*args, split=2)
+    s3 = oracle.contract(*args, split=1)
+    assert np.all(np.abs(s6 - exact) <= 2.0 ** -22 * d)
+    assert np.linalg.norm(s6 - exact) < np.linalg.norm(s3 - exact) / 64
+
+
 def test_golden_fixtures(oracle_lib):
     """Hand-computed small contractions stored as text fixtures."""
     with open(os.path.join(GOLDEN, "tiny_contractions.json")) as f:

@@ -24,10 +24,18 @@ MUTANTS = [
     ("odometer stops one short", "if (++idx[l] < p->ext[l]) break;",
      "if (++idx[l] < p->ext[l] - 1) break;"),
     ("diagonal strides overwritten", "p->sA[slot] += A->strides[d];", "p->sA[slot] = A->strides[d];"),
-    ("split drops lo*hi", "      acc_add(&acc, (double)xl * (double)yh, compensated);\n", "\n"),
+    ("split drops lo*hi",
+     "      acc_add(&acc, (double)xl * (double)yh, compensated);\n    } else if (split == 2) {",
+     "    } else if (split == 2) {"),
     ("split keeps lo*lo instead of hi*lo",
-     "acc_add(&acc, (double)xh * (double)yl, compensated);",
-     "acc_add(&acc, (double)xl * (double)yl, compensated);"),
+     "acc_add(&acc, (double)xh * (double)yl, compensated);\n      acc_add(&acc, (double)xl * (double)yh, compensated);\n    } else if",
+     "acc_add(&acc, (double)xl * (double)yl, compensated);\n      acc_add(&acc, (double)xl * (double)yh, compensated);\n    } else if"),
+    ("bf16x6 drops m*m", "      acc_add(&acc, (double)xm * (double)ym, compensated);\n", "\n"),
+    ("bf16x6 low part from x instead of the residual", "float xl = bf16_rne(xr - xm), yl = bf16_rne(yr - ym);",
+     "float xl = bf16_rne(xr), yl = bf16_rne(yr - ym);"),
+    ("bf16x6 keeps l*m instead of h*l",
+     "acc_add(&acc, (double)xh * (double)yl, compensated);\n      acc_add(&acc, (double)xm * (double)ym, compensated);",
+     "acc_add(&acc, (double)xl * (double)ym, compensated);\n      acc_add(&acc, (double)xm * (double)ym, compensated);"),
     ("bf16 truncation instead of RNE", "u += 0x7fffu + keep_odd;", "u += 0u;"),
     ("bf16 ties away from zero", "u += 0x7fffu + keep_odd;", "u += 0x8000u;"),
     ("C0 read when beta == 0", "double c0 = (beta != 0.0) ? c[offC] : 0.0;",
@@ -54,6 +62,8 @@ CHECKS = [
     lambda: pins.test_bf16_rne_matches_torch(None),
     lambda: pins.test_split_reference_matches_library_split(None),
     lambda: pins.test_split_exact_when_inputs_are_bf16(None),
+    lambda: pins.test_bf16x6_split_matches_library_split(None),
+    lambda: pins.test_bf16x6_error_bound(None),
     lambda: pins.test_golden_fixtures(None),
 ]
 
