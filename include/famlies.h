@@ -77,9 +77,12 @@ typedef int32_t famlies_status;
  * and C in FP64 before storing FP32 (mixed precision: Introduction,
  * "Challenges"; "Supporting new and mixed precisions"; the split sits in
  * the packing step as the paper's footnote on forming T*A^T inside the
- * packing of B does for another transform). */
+ * packing of B does for another transform).  BF16X6 (FAMLIES_F32 only)
+ * splits three ways (h, m = RNE_bf16(x - h), l = RNE_bf16(x - h - m)) and
+ * keeps the six products hh, hm + mh, hl + mm + lh: FP32-level accuracy. */
 #define FAMLIES_NATIVE 0
 #define FAMLIES_BF16X3 1
+#define FAMLIES_BF16X6 2
 
 typedef struct famlies_handle_s *famlies_handle;
 typedef struct famlies_plan_s *famlies_plan;
@@ -122,7 +125,8 @@ famlies_status famlies_destroy(famlies_handle h);
  * vectors -- the "indexing vectors" of the paper's block-scatter mapping --
  * and upload them; choose tile shape and split-K).  UNSUPPORTED when a GEMM
  * dimension reaches 2^31 - 1024.  dtype is FAMLIES_F64 or
- * FAMLIES_F32; compute is FAMLIES_NATIVE or (F32 only) FAMLIES_BF16X3.
+ * FAMLIES_F32; compute is FAMLIES_NATIVE or (F32 only) FAMLIES_BF16X3 or
+ * FAMLIES_BF16X6.
  * A label summed inside one input is contracted against a zero stride in
  * the other operand (the product runs over it), so it costs MFMA work. */
 famlies_status famlies_plan_contract(famlies_handle h, famlies_plan *out, int dtype, int compute,

@@ -40,6 +40,7 @@ FAMLIES_F64 = 1
 FAMLIES_F32 = 2
 FAMLIES_NATIVE = 0
 FAMLIES_BF16X3 = 1
+FAMLIES_BF16X6 = 2
 
 ERROR_NAMES = {
     FAMLIES_ERR_INVALID_ARG: "INVALID_ARG", FAMLIES_ERR_SHAPE_MISMATCH: "SHAPE_MISMATCH",
@@ -275,7 +276,9 @@ def _compute_code(compute: str) -> int:
         return FAMLIES_NATIVE
     if compute == "bf16x3":
         return FAMLIES_BF16X3
-    raise ValueError("compute must be 'native' or 'bf16x3'")
+    if compute == "bf16x6":
+        return FAMLIES_BF16X6
+    raise ValueError("compute must be 'native', 'bf16x3' or 'bf16x6'")
 
 
 def _labels(l) -> Tuple[int, ...]:

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfamlies.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["abi.hip", "planner.cpp", "table.cpp", "plain_kernels.hip", "bf16x3_kernels.hip",
+SOURCES = ["abi.hip", "planner.cpp", "table.cpp", "plain_kernels.hip", "split_kernels.hip",
            "batch.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

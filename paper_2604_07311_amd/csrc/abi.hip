@@ -259,15 +259,17 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   p->an = an;
   p->index_bits = index_bits_for(an);
   p->cfg = force ? *force : choose_tiles(h, an);
-  if (compute == FAMLIES_BF16X3) {
+  const int ns = split_parts(compute);
+  if (ns) {
     p->cfg.bk = 32;
-    // large problems: a 256 x 128 tile (128 x 64 per wave) halves the LDS
-    // bytes per MFMA that the 128 x 128 tile needs
-    if (!force && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1) {
+    // bf16x3 on large problems: a 256 x 128 tile (128 x 64 per wave) halves
+    // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 has three
+    // accumulators per block and stays at 128 x 128)
+    if (!force && ns == 2 && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1) {
       p->cfg.bm = 256;
       p->cfg.bn = 128;
     }
-    if (!bf16x3_tile_supported(p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
+    if (!split_tile_supported(ns, p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
   } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
     p->cfg.bm = p->cfg.bn = 128;
     p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
@@ -289,7 +291,7 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
       return st;
     }
     if (p->cfg.split > 1 && an.K > 0) {
-      const size_t es = compute == FAMLIES_BF16X3 ? 8 : (size_t)an.esize;
+      const size_t es = ns ? 8 : (size_t)an.esize;
       p->work_bytes = (size_t)p->cfg.split * (size_t)mp * (size_t)np * es;
       hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
       if (e != hipSuccess) {
@@ -402,7 +404,7 @@ famlies_status famlies_plan_destroy(famlies_plan p) {
 
 famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info* info) {
   if (!p || !is_live(p) || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
-  fill_info(p->an, p->cfg, p->index_bits, p->an.compute == FAMLIES_BF16X3 ? 2 : 1, info);
+  fill_info(p->an, p->cfg, p->index_bits, 1 + split_parts(p->an.compute), info);
   return FAMLIES_OK;
 }
 
@@ -440,9 +442,10 @@ famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, cons
   L.yk = an.y_kfast;
   L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
   hipError_t e;
-  if (an.compute == FAMLIES_BF16X3 && L.kind == PlainLaunch::kMain) {
-    e = p->index_bits == 32 ? launch_bf16x3(make_args<uint32_t>(p, x, y, C, alpha, beta), L, s)
-                            : launch_bf16x3(make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
+  const int ns = split_parts(an.compute);
+  if (ns && L.kind == PlainLaunch::kMain) {
+    e = p->index_bits == 32 ? launch_split(make_args<uint32_t>(p, x, y, C, alpha, beta), L, ns, s)
+                            : launch_split(make_args<int64_t>(p, x, y, C, alpha, beta), L, ns, s);
   } else {
     e = p->index_bits == 32 ? launch_plain(an.dtype, make_args<uint32_t>(p, x, y, C, alpha, beta), L, s)
                             : launch_plain(an.dtype, make_args<int64_t>(p, x, y, C, alpha, beta), L, s);

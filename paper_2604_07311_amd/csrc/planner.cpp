@@ -133,12 +133,12 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
     *err = "dtype must be FAMLIES_F64 or FAMLIES_F32";
     return FAMLIES_ERR_INVALID_ARG;
   }
-  if (compute != FAMLIES_NATIVE && compute != FAMLIES_BF16X3) {
-    *err = "compute must be FAMLIES_NATIVE or FAMLIES_BF16X3";
+  if (compute != FAMLIES_NATIVE && compute != FAMLIES_BF16X3 && compute != FAMLIES_BF16X6) {
+    *err = "compute must be FAMLIES_NATIVE, FAMLIES_BF16X3 or FAMLIES_BF16X6";
     return FAMLIES_ERR_INVALID_ARG;
   }
-  if (compute == FAMLIES_BF16X3 && dtype != FAMLIES_F32) {
-    *err = "bf16x3 compute needs FAMLIES_F32 data";
+  if (compute != FAMLIES_NATIVE && dtype != FAMLIES_F32) {
+    *err = "split-bf16 compute needs FAMLIES_F32 data";
     return FAMLIES_ERR_UNSUPPORTED;
   }
   if (!check_tensor(A, "A", err) || !check_tensor(B, "B", err) || !check_tensor(C, "C", err))

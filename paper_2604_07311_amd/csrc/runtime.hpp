@@ -79,8 +79,10 @@ famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, i
                          const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
                          const TileCfg* force);
 
-hipError_t launch_bf16x3(const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s);
-hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s);
-bool bf16x3_tile_supported(int bm, int bn);
+// Split-bf16 kernels: ns = 2 (bf16x3) or 3 (bf16x6) parts per operand.
+hipError_t launch_split(const PlainArgs<uint32_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
+hipError_t launch_split(const PlainArgs<int64_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
+bool split_tile_supported(int ns, int bm, int bn);
+inline int split_parts(int compute) { return compute == FAMLIES_BF16X6 ? 3 : compute == FAMLIES_BF16X3 ? 2 : 0; }
 
 }  // namespace famlies

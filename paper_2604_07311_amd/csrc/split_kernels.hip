@@ -1,13 +1,15 @@
-// bf16x3 precision path: FP32 data, products on BF16 MFMA.
+// Split-bf16 precision paths: FP32 data, products on BF16 MFMA.
 //
 // Each FP32 operand value x is split while it is staged into LDS (the
 // transform sits inside the packing step, as the paper does for T*A^T in its
-// footnote on the sandwiched GEMM C := C - A T A^T):
-//     hi = RNE_bf16(x),   lo = RNE_bf16(x - hi)      (x - hi is exact in FP32)
-// and  x*y ~= hi_x*hi_y + (hi_x*lo_y + lo_x*hi_y), dropping lo_x*lo_y.
-// The hi*hi products accumulate in one FP32 MFMA accumulator, the two cross
-// products in a second; the epilogue combines them with alpha, beta and C in
-// FP64 and stores FP32 (new and mixed precisions: Introduction,
+// footnote on the sandwiched GEMM C := C - A T A^T) into NS bf16 parts:
+//   bf16x3 (NS = 2): h = RNE_bf16(x), l = RNE_bf16(x - h);
+//                    x*y ~= hh + (hl + lh)              (3 products)
+//   bf16x6 (NS = 3): h, m = RNE_bf16(x - h), l = RNE_bf16(x - h - m);
+//                    x*y ~= hh + (hm + mh) + (hl + mm + lh)   (6 products)
+// (every difference is exact in FP32).  Products of the same order go to one
+// FP32 MFMA accumulator; the epilogue adds the orders in FP64 together with
+// alpha, beta and C, and stores FP32 (new and mixed precisions: Introduction,
 // "Challenges"; "Supporting new and mixed precisions").
 #include "device.hpp"
 #include "runtime.hpp"
@@ -24,62 +26,67 @@ __device__ __forceinline__ f32x16 mma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// Split two floats into packed bf16 pairs hi (RNE of x) and lo (RNE of
-// x - hi; the difference is exact in FP32).
-__device__ __forceinline__ void split2(float x0, float x1, uint32_t* hi, uint32_t* lo) {
-  const f32x2 x = {x0, x1};
-  const bf16x2 h = __builtin_convertvector(x, bf16x2);
-  const f32x2 r = x - __builtin_convertvector(h, f32x2);
-  const bf16x2 l = __builtin_convertvector(r, bf16x2);
-  *hi = __builtin_bit_cast(uint32_t, h);
-  *lo = __builtin_bit_cast(uint32_t, l);
+// Split two floats into NS packed bf16 pairs (part t of both values in
+// parts[t]); each residual x - (parts so far) is exact in FP32.
+template <int NS>
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t* parts) {
+  f32x2 r = {x0, x1};
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const bf16x2 h = __builtin_convertvector(r, bf16x2);
+    parts[t] = __builtin_bit_cast(uint32_t, h);
+    if (t + 1 < NS) r = r - __builtin_convertvector(h, f32x2);
+  }
 }
 
 // bf16 LDS tiles: [row][k] with 16-byte aligned rows of BK + 8 entries.
 constexpr int kB3K = 32;            // contraction slice per stage
 constexpr int kB3LD = kB3K + 8;     // row pitch in bf16
 
-// Write the split of a gathered slice into the hi and lo tiles.  K-gathered
-// threads own pairs of consecutive k's (one packed dword per row and part);
-// row-gathered threads own a run of k's in one row (8-byte stores).
-template <typename G, bool KFAST>
-__device__ __forceinline__ void store_split(const G& gg, __bf16* hi, __bf16* lo, int k0, int kend) {
+// Write the split of a gathered slice into the NS part tiles (part t at
+// tiles + t * tile_elems).  K-gathered threads own pairs of consecutive k's
+// (one packed dword per row and part); row-gathered threads own a run of k's
+// in one row (8-byte stores).
+template <int NS, typename G, bool KFAST>
+__device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile_elems, int k0, int kend) {
   if constexpr (KFAST) {
     static_assert(G::KVT == 2, "K-gathered bf16 split stores pairs of k");
 #pragma unroll
     for (int i = 0; i < G::E / 2; ++i) {
-      uint32_t h, l;
-      split2(gg.value(2 * i, k0, kend), gg.value(2 * i + 1, k0, kend), &h, &l);
+      uint32_t p[NS];
+      split2<NS>(gg.value(2 * i, k0, kend), gg.value(2 * i + 1, k0, kend), p);
       const int idx = gg.lds_index(2 * i, kB3LD);
-      *reinterpret_cast<uint32_t*>(hi + idx) = h;
-      *reinterpret_cast<uint32_t*>(lo + idx) = l;
+#pragma unroll
+      for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
     }
   } else {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int q = 0; q < G::E / 4; ++q) {
-      uint32_t h0, l0, h1, l1;
-      split2(gg.value(4 * q, k0, kend), gg.value(4 * q + 1, k0, kend), &h0, &l0);
-      split2(gg.value(4 * q + 2, k0, kend), gg.value(4 * q + 3, k0, kend), &h1, &l1);
-      const u32x2 h = {h0, h1}, l = {l0, l1};
+      uint32_t p0[NS], p1[NS];
+      split2<NS>(gg.value(4 * q, k0, kend), gg.value(4 * q + 1, k0, kend), p0);
+      split2<NS>(gg.value(4 * q + 2, k0, kend), gg.value(4 * q + 3, k0, kend), p1);
       const int idx = gg.lds_index(4 * q, kB3LD);
-      *reinterpret_cast<u32x2*>(hi + idx) = h;
-      *reinterpret_cast<u32x2*>(lo + idx) = l;
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const u32x2 w = {p0[t], p1[t]};
+        *reinterpret_cast<u32x2*>(tiles + t * tile_elems + idx) = w;
+      }
     }
   }
 }
 
 // One workgroup: a BM x BN tile of C, 2 x 2 waves of (BM/2) x (BN/2), each
 // made of 32 x 32 MFMA blocks.
-template <typename OffT, int BM, int BN, bool XK, bool YK>
-__global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
+template <typename OffT, int BM, int BN, bool XK, bool YK, int NS>
+__global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   constexpr int BK = kB3K;
   using GX = TileGather<float, OffT, BM, BK, XK, XK ? 2 : 1>;
   using GY = TileGather<float, OffT, BN, BK, YK, YK ? 2 : 1>;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
-  constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per tile
-  constexpr int STAGE = 2 * XS + 2 * YS;           // hi and lo of both tiles
+  constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per part tile
+  constexpr int STAGE = NS * (XS + YS);            // all parts of both tiles
   __shared__ __attribute__((aligned(16))) __bf16 smem[2 * STAGE];
 
   const int tid = threadIdx.x;
@@ -105,20 +112,19 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
   gx.init(a.xmn, m0, tid);
   gy.init(a.ymn, n0, tid);
 
-  f32x16 hh[MB][NB], mid[MB][NB];
+  f32x16 acc[NS][MB][NB];  // acc[o]: products whose parts' orders sum to o
 #pragma unroll
-  for (int i = 0; i < MB; ++i)
+  for (int o = 0; o < NS; ++o)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      hh[i][j] = f32x16{};
-      mid[i][j] = f32x16{};
-    }
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[o][i][j] = f32x16{};
 
   const int g = lane / 32, r = lane % 32;
   auto stage_store = [&](int buf, int k0) {
     __bf16* base = smem + buf * STAGE;
-    store_split<GX, XK>(gx, base, base + XS, k0, kend);
-    store_split<GY, YK>(gy, base + 2 * XS, base + 2 * XS + YS, k0, kend);
+    store_split<NS, GX, XK>(gx, base, XS, k0, kend);
+    store_split<NS, GY, YK>(gy, base + NS * XS, YS, k0, kend);
   };
   if (nk > 0) {
     gx.fetch_k(a.xk, kbeg);
@@ -142,40 +148,42 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
           gy.fetch_k(a.yk, kbeg + (it + 2) * BK);
         }
       }
-      const __bf16* xh = smem + cur * STAGE;
-      const __bf16* xl = xh + XS;
-      const __bf16* yh = xh + 2 * XS;
-      const __bf16* yl = yh + YS;
+      const __bf16* xs = smem + cur * STAGE;
+      const __bf16* ys = xs + NS * XS;
       // lane group g covers k in [16g, 16g + 16) of the slice, in two steps of 8
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        bf16x8 ah[MB], al[MB], bh[NB], bl[NB];
+        bf16x8 av[NS][MB], bv[NS][NB];
 #pragma unroll
-        for (int i = 0; i < MB; ++i) {
-          const int o = (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8;
-          ah[i] = *reinterpret_cast<const bf16x8*>(xh + o);
-          al[i] = *reinterpret_cast<const bf16x8*>(xl + o);
-        }
+        for (int p = 0; p < NS; ++p) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int o = (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8;
-          bh[j] = *reinterpret_cast<const bf16x8*>(yh + o);
-          bl[j] = *reinterpret_cast<const bf16x8*>(yl + o);
+          for (int i = 0; i < MB; ++i)
+            av[p][i] = *reinterpret_cast<const bf16x8*>(xs + p * XS + (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8);
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            bv[p][j] = *reinterpret_cast<const bf16x8*>(ys + p * YS + (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8);
         }
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            hh[i][j] = mma_bf16(ah[i], bh[j], hh[i][j]);
-            mid[i][j] = mma_bf16(ah[i], bl[j], mid[i][j]);
-            mid[i][j] = mma_bf16(al[i], bh[j], mid[i][j]);
-          }
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int pa = 0; pa < NS; ++pa)
+#pragma unroll
+              for (int pb = 0; pa + pb < NS; ++pb)
+                acc[pa + pb][i][j] = mma_bf16(av[pa][i], bv[pb][j], acc[pa + pb][i][j]);
       }
       if (more) stage_store(cur ^ 1, kbeg + (it + 1) * BK);
       __syncthreads();
     }
   }
 
+  auto total = [&](int i, int j, int e) {
+    double v = 0.0;
+#pragma unroll
+    for (int o = NS - 1; o >= 0; --o) v += (double)acc[o][i][j][e];  // smallest order first
+    return v;
+  };
   if (a.splits == 1) {
     float* __restrict__ C = static_cast<float*>(a.c) + a.cl[l];
 #pragma unroll
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
           const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
           if (m < a.M && n < a.N) {
             float* cp = at(C, (OffT)(a.cm[m] + cn));
-            double v = a.alpha * ((double)hh[i][j][e] + (double)mid[i][j][e]);
+            double v = a.alpha * total(i, j, e);
             if (a.beta != 0.0) v += a.beta * (double)*cp;
             *cp = (float)v;
           }
@@ -206,14 +214,14 @@ __global__ __launch_bounds__(kThreads) void bf16x3_contract(PlainArgs<OffT> a) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
-          W[(size_t)m * ldw + n] = (double)hh[i][j][e] + (double)mid[i][j][e];
+          W[(size_t)m * ldw + n] = total(i, j, e);
         }
     }
   }
 }
 
 template <typename OffT>
-__global__ __launch_bounds__(kThreads) void bf16x3_reduce(PlainArgs<OffT> a, int ldw, int rows) {
+__global__ __launch_bounds__(kThreads) void split_reduce(PlainArgs<OffT> a, int ldw, int rows) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= (int64_t)a.M * a.N) return;
   const int m = (int)(i / a.N), n = (int)(i % a.N);
@@ -227,43 +235,51 @@ __global__ __launch_bounds__(kThreads) void bf16x3_reduce(PlainArgs<OffT> a, int
   *cp = (float)v;
 }
 
-template <typename OffT, int BM, int BN>
-static hipError_t launch_b3_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int grid, hipStream_t s) {
+template <typename OffT, int BM, int BN, int NS>
+static hipError_t launch_split_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int grid, hipStream_t s) {
   if (xk && yk)
-    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, true, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((split_contract<OffT, BM, BN, true, true, NS>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (xk)
-    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, true, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((split_contract<OffT, BM, BN, true, false, NS>), dim3(grid), dim3(kThreads), 0, s, a);
   else if (yk)
-    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((split_contract<OffT, BM, BN, false, true, NS>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((bf16x3_contract<OffT, BM, BN, false, false>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((split_contract<OffT, BM, BN, false, false, NS>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename OffT>
-static hipError_t launch_b3(const PlainArgs<OffT>& a, const PlainLaunch& L, hipStream_t s) {
+static hipError_t launch_split_t(const PlainArgs<OffT>& a, const PlainLaunch& L, int ns, hipStream_t s) {
   const int grid = a.tiles_m * a.tiles_n * a.splits * a.L;
   hipError_t e = hipErrorInvalidValue;
-  if (L.bm == 256 && L.bn == 128)
-    e = launch_b3_tile<OffT, 256, 128>(a, L.xk, L.yk, grid, s);
-  else if (L.bm == 128 && L.bn == 128)
-    e = launch_b3_tile<OffT, 128, 128>(a, L.xk, L.yk, grid, s);
-  else if (L.bm == 64 && L.bn == 64)
-    e = launch_b3_tile<OffT, 64, 64>(a, L.xk, L.yk, grid, s);
+  if (ns == 2) {
+    if (L.bm == 256 && L.bn == 128)
+      e = launch_split_tile<OffT, 256, 128, 2>(a, L.xk, L.yk, grid, s);
+    else if (L.bm == 128 && L.bn == 128)
+      e = launch_split_tile<OffT, 128, 128, 2>(a, L.xk, L.yk, grid, s);
+    else if (L.bm == 64 && L.bn == 64)
+      e = launch_split_tile<OffT, 64, 64, 2>(a, L.xk, L.yk, grid, s);
+  } else if (ns == 3) {
+    if (L.bm == 128 && L.bn == 128)
+      e = launch_split_tile<OffT, 128, 128, 3>(a, L.xk, L.yk, grid, s);
+    else if (L.bm == 64 && L.bn == 64)
+      e = launch_split_tile<OffT, 64, 64, 3>(a, L.xk, L.yk, grid, s);
+  }
   if (e != hipSuccess || a.splits == 1) return e;
   const int64_t mn = (int64_t)a.M * a.N;
-  hipLaunchKernelGGL((bf16x3_reduce<OffT>), dim3((int)((mn + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+  hipLaunchKernelGGL((split_reduce<OffT>), dim3((int)((mn + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      s, a, a.tiles_n * L.bn, a.tiles_m * L.bm);
   return hipGetLastError();
 }
 
-hipError_t launch_bf16x3(const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s) {
-  return launch_b3(a, L, s);
+hipError_t launch_split(const PlainArgs<uint32_t>& a, const PlainLaunch& L, int ns, hipStream_t s) {
+  return launch_split_t(a, L, ns, s);
 }
-hipError_t launch_bf16x3(const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {
-  return launch_b3(a, L, s);
+hipError_t launch_split(const PlainArgs<int64_t>& a, const PlainLaunch& L, int ns, hipStream_t s) {
+  return launch_split_t(a, L, ns, s);
 }
-bool bf16x3_tile_supported(int bm, int bn) {
+bool split_tile_supported(int ns, int bm, int bn) {
+  if (ns == 3) return (bm == 128 && bn == 128) || (bm == 64 && bn == 64);
   return (bm == 256 && bn == 128) || (bm == 128 && bn == 128) || (bm == 64 && bn == 64);
 }
 

@@ -103,3 +103,43 @@ def test_bf16x3_split_k(gpu):
                                want_cond=True)
     got = gpu.run(p, "f32", compute="bf16x3")
     assert np.all(np.abs(got - exact) <= bf16x3_bound(4000, _d_prod(p), d))
+
+
+# ------------------------------------------------------------------ bf16x6
+def test_bf16x6_integer_exact(gpu):
+    rng = np.random.default_rng(87)
+    p = synth.random_problem(rng, lo=4, hi=30)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    np.testing.assert_array_equal(gpu.run(p, "f32", compute="bf16x6"), want)
+
+
+@pytest.mark.parametrize("case", ["ladder", "random"])
+def test_bf16x6_fp32_level_accuracy(gpu, case):
+    """bf16x6 against the oracle's split-exact bf16x6 reference (only the FP32
+    accumulation differs) and against the exact result at the FP32 bound."""
+    rng = np.random.default_rng(88)
+    if case == "ladder":
+        p = synth.ladder(20, 6, seed=89, dist="outliers")
+    else:
+        p = synth.random_problem(rng, lo=6, hi=40)
+        p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "outliers") for t in (p.a, p.b, p.c))
+    p = round_inputs(p, "f32")
+    K = synth.sizes(p)[2]
+    used = np.zeros(p.cbuf.size, dtype=bool)
+    used[used_offsets(p.c)] = True
+    args = (p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    exact, d = oracle.contract(*args, want_cond=True)
+    split6 = oracle.contract(*args, split=2)
+    dp = _d_prod(p)
+    got = gpu.run(p, "f32", compute="bf16x6")
+    f32 = gpu.run(p, "f32")
+    u = used
+    acc = gamma(3 * K, 2.0 ** -23) * (1 + 2.0 ** -7) * dp + 2.0 ** -23 * d
+    assert np.all(np.abs(got[u] - split6[u]) <= acc[u])
+    # dropped terms (m*l, l*m, l*l) add at most 2^-22 |a||b| per product
+    assert np.all(np.abs(got[u] - exact[u]) <= (2.0 ** -22 * dp + acc)[u])
+    e6 = np.linalg.norm(got[u] - exact[u]) / np.linalg.norm(exact[u])
+    e32 = np.linalg.norm(f32[u] - exact[u]) / np.linalg.norm(exact[u])
+    note("%s K=%d  bf16x6 rel err %.3e   fp32 rel err %.3e" % (case, K, e6, e32))
+    assert e6 < 4 * e32 + 1e-7
