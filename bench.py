@@ -91,7 +91,7 @@ class Single:
         self.p, self.dtype, self.compute = p, dtype, compute
         self.fm, self.torch = fm, torch
         code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-        comp = fm.FAMLIES_BF16X3 if compute == "bf16x3" else fm.FAMLIES_NATIVE
+        comp = {"bf16x3": fm.FAMLIES_BF16X3, "bf16x6": fm.FAMLIES_BF16X6}.get(compute, fm.FAMLIES_NATIVE)
         t0 = time.perf_counter()
         self.plan = fm.famlies_plan_contract(fm.handle(0), code, comp,
                                              fm.make_desc(p.a.extents, p.a.strides, p.la),
@@ -234,7 +234,7 @@ def wl_ladder(args):
 
 def _fp32_vs_bf16x3(args, p, name):
     res = {}
-    for comp in ("native", "bf16x3"):
+    for comp in ("native", "bf16x3", "bf16x6"):
         s = Single(p, "f32", comp)
         check = sample_check(p, s.result_once(), "f32", n=1024)
         ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
@@ -255,6 +255,11 @@ def _fp32_vs_bf16x3(args, p, name):
                    "pct_mfma_peak": round(100 * flops / (r32["ms"] * 1e-3) / PEAK["f32"], 2),
                    "error_vs_fp64": r32["check"]}
     out["speedup_vs_fp32"] = round(r32["ms"] / r3["ms"], 3)
+    r6 = res["bf16x6"]
+    out["bf16x6"] = {"ms_per_step": round(r6["ms"], 4),
+                     "value": round(flops / (r6["ms"] * 1e-3) / 1e9, 2),
+                     "speedup_vs_fp32": round(r32["ms"] / r6["ms"], 3),
+                     "error_vs_fp64": r6["check"]}
     out["roofline"] = roofline(3 * flops, r3["launch"], PEAK["bf16"])
     return out
 
