@@ -114,6 +114,36 @@ class Single:
         self.fm.famlies_execute(self.plan, self.p.alpha, self.ptrs[0], self.ptrs[1], self.p.beta,
                                 self.ptrs[2], self.stream.cuda_stream)
 
+    def packed(self, mask, steps, warmup):
+        """Pack the operands in `mask` (bit 0: A, bit 1: B) once, then time
+        famlies_execute_packed.  Returns (pack ms, ms per step, check input)."""
+        torch, fm = self.torch, self.fm
+        bufs, ptrs = {}, list(self.ptrs[:2])
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(self.stream)
+        for op in (0, 1):
+            if mask & (1 << op):
+                n = fm.famlies_pack_size(self.plan, op)
+                bufs[op] = torch.empty(n // 4 + 4, dtype=torch.int32, device=self.c.device)
+                fm.famlies_pack(self.plan, op, self.ptrs[op], bufs[op].data_ptr(), self.stream.cuda_stream)
+                ptrs[op] = bufs[op].data_ptr()
+        e1.record(self.stream)
+        torch.cuda.synchronize()
+        pack_ms = e0.elapsed_time(e1)
+
+        def step():
+            fm.famlies_execute_packed(self.plan, self.p.alpha, ptrs[0], ptrs[1], self.p.beta,
+                                      self.ptrs[2], mask, self.stream.cuda_stream)
+
+        self.c.copy_(self.c0)
+        step()
+        torch.cuda.synchronize()
+        got = self.c.cpu().numpy().astype(np.float64)
+        ms, launch, _ = Timer(self.stream).run(step, steps, warmup)
+        del bufs
+        return pack_ms, ms, launch, got
+
     def result_once(self):
         """C after one call from C0 (float64 numpy storage)."""
         self.c.copy_(self.c0)
@@ -205,6 +235,14 @@ def wl_ladder(args):
         ms, launch, lmin = Timer(s.stream).run(s.step, args.steps, args.warmup)
         res[dtype] = {"ms": ms, "launch": launch, "info": s.info, "check": check, "plan_s": s.plan_s}
         log("%s: %.3f ms/step (%.1f GFLOP/s) check %s" % (dtype, ms, s.info["flops"] / ms / 1e6, check))
+        if args.pack:
+            # W (operand A) pre-packed once, as a CC code reusing it across iterations would
+            pack_ms, pms, plaunch, got = s.packed(1, args.steps, args.warmup)
+            res[dtype]["packed_W"] = {"pack_ms_once": round(pack_ms, 3), "ms_per_step": round(pms, 4),
+                                      "value": round(s.info["flops"] / (pms * 1e-3) / 1e9, 2),
+                                      "pct_mfma_peak": round(100 * s.info["flops"] / (pms * 1e-3) / PEAK[dtype], 2),
+                                      "error_vs_fp64": sample_check(p, got, dtype, n=512)}
+            log("%s packed W: pack %.2f ms once, %.3f ms/step" % (dtype, pack_ms, pms))
         s.close()
     head = "f64" if "f64" in res else list(res)[0]
     r = res[head]
@@ -218,6 +256,8 @@ def wl_ladder(args):
     out["pct_mfma_peak"] = round(100 * flops / (r["ms"] * 1e-3) / PEAK[head], 2)
     out["error_vs_fp64"] = r["check"]
     out["roofline"] = roofline(flops, r["launch"], PEAK[head])
+    if "packed_W" in r:
+        out["packed_W"] = r["packed_W"]
     for dt, rr in res.items():
         if dt == head:
             continue
@@ -226,6 +266,8 @@ def wl_ladder(args):
             "value": round(v / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(rr["ms"], 4),
             "pct_mfma_peak": round(100 * v / PEAK[dt], 2), "error_vs_fp64": rr["check"],
             "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt])}
+        if "packed_W" in rr:
+            out["secondary"][dt]["packed_W"] = rr["packed_W"]
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(probs[head])
@@ -240,6 +282,12 @@ def _fp32_vs_bf16x3(args, p, name):
         ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
         res[comp] = {"ms": ms, "launch": launch, "info": s.info, "check": check}
         log("%s %s: %.3f ms (%.1f GFLOP/s) check %s" % (name, comp, ms, s.info["flops"] / ms / 1e6, check))
+        if args.pack and comp == "bf16x3":
+            pack_ms, pms, plaunch, got = s.packed(3, args.steps, args.warmup)
+            res[comp]["packed"] = {"pack_ms_once": round(pack_ms, 3), "ms_per_step": round(pms, 4),
+                                   "gflops_fp32_equivalent": round(s.info["flops"] / (pms * 1e-3) / 1e9, 2),
+                                   "error_vs_fp64": sample_check(p, got, "f32", n=512)}
+            log("%s bf16x3 packed A and B: pack %.2f ms once, %.3f ms/step" % (name, pack_ms, pms))
         s.close()
     r3, r32 = res["bf16x3"], res["native"]
     flops = r3["info"]["flops"]
@@ -255,6 +303,8 @@ def _fp32_vs_bf16x3(args, p, name):
                    "pct_mfma_peak": round(100 * flops / (r32["ms"] * 1e-3) / PEAK["f32"], 2),
                    "error_vs_fp64": r32["check"]}
     out["speedup_vs_fp32"] = round(r32["ms"] / r3["ms"], 3)
+    if "packed" in r3:
+        out["packed_operands"] = r3["packed"]
     r6 = res["bf16x6"]
     out["bf16x6"] = {"ms_per_step": round(r6["ms"], 4),
                      "value": round(flops / (r6["ms"] * 1e-3) / 1e9, 2),
@@ -437,6 +487,8 @@ def main():
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pack", action="store_true",
+                    help="also time the pre-packed path (ladder: W packed once; ring: both operands)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size "
                          "reference kernel for the HBM byte counters)")

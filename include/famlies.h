@@ -46,6 +46,7 @@
 #ifndef FAMLIES_H
 #define FAMLIES_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -170,6 +171,24 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan *out, int dtype
 famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta,
                                      const void *const *A_dev, const void *const *B_dev,
                                      void *const *C_dev, void *stream);
+
+/* Pre-packing (the packing step hoisted out of repeated calls, for an
+ * operand that many contractions read: Girder 2, "Enabling optimizations
+ * across layers").  famlies_pack writes user operand `operand` (0 = A,
+ * 1 = B; src is its base pointer as for famlies_execute) into dst in the
+ * plan's tile order -- blocks of tile rows x tile_k contracted indices,
+ * [row][k], zero-filled past the edges, and for the split-bf16 modes already
+ * split into bf16 parts -- so that famlies_execute_packed copies whole tiles
+ * instead of gathering and splitting.  dst must hold famlies_pack_size bytes
+ * and be 16-byte aligned; it is owned by the caller and valid for this plan
+ * only.  UNSUPPORTED for plans whose tile is not 128 x 128 (256 x 128 also for
+ * bf16x3) or whose offsets need 64 bits.  Asynchronous on `stream`. */
+famlies_status famlies_pack_size(famlies_plan p, int operand, size_t *bytes);
+famlies_status famlies_pack(famlies_plan p, int operand, const void *src, void *dst, void *stream);
+/* As famlies_execute, where bit 0 of `packed` says A points to a buffer
+ * written by famlies_pack (operand 0) and bit 1 the same for B. */
+famlies_status famlies_execute_packed(famlies_plan p, double alpha, const void *A, const void *B,
+                                      double beta, void *C, int packed, void *stream);
 
 /* Autotune: time the candidate tile shapes on synthetic problems of each
  * size class on the handle's device and write the table to table_path

@@ -74,7 +74,7 @@ EXPORTS = [
     "famlies_create", "famlies_destroy", "famlies_plan_contract", "famlies_execute",
     "famlies_plan_destroy", "famlies_plan_get_info", "famlies_analyze", "famlies_batch_plan",
     "famlies_batch_execute", "famlies_tune", "famlies_load_tune_table", "famlies_last_error",
-    "famlies_version",
+    "famlies_version", "famlies_pack_size", "famlies_pack", "famlies_execute_packed",
 ]
 
 
@@ -113,6 +113,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "famlies_batch_execute": ([vp, dbl, dbl, vp, vp, vp, vp], i32),
             "famlies_tune": ([vp, ctypes.c_char_p, i32], i32),
             "famlies_load_tune_table": ([vp, ctypes.c_char_p], i32),
+            "famlies_pack_size": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
+            "famlies_pack": ([vp, i32, vp, vp, vp], i32),
+            "famlies_execute_packed": ([vp, dbl, vp, vp, dbl, vp, i32, vp], i32),
             "famlies_last_error": ([], ctypes.c_char_p),
             "famlies_version": ([], ctypes.c_char_p),
         }
@@ -176,6 +179,22 @@ def famlies_execute(plan: int, alpha: float, A_ptr: int, B_ptr: int, beta: float
                     stream: int = 0) -> None:
     _check(load_library().famlies_execute(plan, float(alpha), A_ptr, B_ptr, float(beta), C_ptr,
                                           stream), "famlies_execute")
+
+
+def famlies_pack_size(plan: int, operand: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().famlies_pack_size(plan, int(operand), ctypes.byref(n)), "famlies_pack_size")
+    return n.value
+
+
+def famlies_pack(plan: int, operand: int, src_ptr: int, dst_ptr: int, stream: int = 0) -> None:
+    _check(load_library().famlies_pack(plan, int(operand), src_ptr, dst_ptr, stream), "famlies_pack")
+
+
+def famlies_execute_packed(plan: int, alpha: float, A_ptr: int, B_ptr: int, beta: float, C_ptr: int,
+                           packed: int, stream: int = 0) -> None:
+    _check(load_library().famlies_execute_packed(plan, float(alpha), A_ptr, B_ptr, float(beta), C_ptr,
+                                                 int(packed), stream), "famlies_execute_packed")
 
 
 def famlies_plan_destroy(plan: int) -> None:

@@ -228,6 +228,8 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   a.N = (int32_t)p->an.N;
   a.K = (int32_t)p->an.K;
   a.L = (int32_t)p->an.L;
+  a.x_nkb = 0;
+  a.y_nkb = 0;
   a.tiles_m = (int32_t)ceil_div(p->an.M, p->cfg.bm);
   a.tiles_n = (int32_t)ceil_div(p->an.N, p->cfg.bn);
   a.splits = p->cfg.split;
@@ -416,8 +418,8 @@ static bool overlaps(const void* p, int64_t plo, int64_t phi, const void* q, int
   return a0 < b1 && b0 < a1;
 }
 
-famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, const void* B, double beta,
-                               void* C, void* stream) {
+static famlies_status execute_impl(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+                                   void* C, int packed, void* stream) {
   if (!p || !is_live(p) || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute: invalid plan");
   const Analysis& an = p->an;
   if (an.M == 0 || an.N == 0) return FAMLIES_OK;
@@ -426,32 +428,82 @@ famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, cons
   const uintptr_t al = (uintptr_t)an.esize - 1;
   if (((uintptr_t)C & al) || (need_ab && (((uintptr_t)A & al) || ((uintptr_t)B & al))))
     return fail(FAMLIES_ERR_ALIGN, "famlies_execute: data pointer not aligned to its element size");
-  if (need_ab && (overlaps(C, an.c_lo, an.c_hi, A, an.a_lo, an.a_hi, an.esize) ||
-                  overlaps(C, an.c_lo, an.c_hi, B, an.b_lo, an.b_hi, an.esize)))
+  const bool pa = packed & 1, pb = packed & 2;
+  size_t sza = 0, szb = 0;
+  if (need_ab && pa) {
+    famlies_status st = famlies_pack_size(p, 0, &sza);
+    if (st != FAMLIES_OK) return st;
+    if ((uintptr_t)A & 15) return fail(FAMLIES_ERR_ALIGN, "famlies_execute_packed: packed A not 16-byte aligned");
+  }
+  if (need_ab && pb) {
+    famlies_status st = famlies_pack_size(p, 1, &szb);
+    if (st != FAMLIES_OK) return st;
+    if ((uintptr_t)B & 15) return fail(FAMLIES_ERR_ALIGN, "famlies_execute_packed: packed B not 16-byte aligned");
+  }
+  const int64_t es = an.esize;
+  auto packed_overlap = [&](const void* q, size_t bytes) {
+    return overlaps(C, an.c_lo, an.c_hi, q, 0, (int64_t)(bytes / (size_t)es) - 1, an.esize);
+  };
+  if (need_ab && ((pa ? packed_overlap(A, sza) : overlaps(C, an.c_lo, an.c_hi, A, an.a_lo, an.a_hi, an.esize)) ||
+                  (pb ? packed_overlap(B, szb) : overlaps(C, an.c_lo, an.c_hi, B, an.b_lo, an.b_hi, an.esize))))
     return fail(FAMLIES_ERR_ALIAS, "famlies_execute: C overlaps A or B");
   DeviceGuard dg(p->h->device);
   if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the plan's device");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* x = an.swapped ? B : A;
   const void* y = an.swapped ? A : B;
+  const bool xp = an.swapped ? pb : pa, yp = an.swapped ? pa : pb;
   PlainLaunch L;
   L.bm = p->cfg.bm;
   L.bn = p->cfg.bn;
   L.bk = p->cfg.bk;
-  L.xk = an.x_kfast;
-  L.yk = an.y_kfast;
+  L.xm = xp ? 2 : (an.x_kfast ? 1 : 0);
+  L.ym = yp ? 2 : (an.y_kfast ? 1 : 0);
   L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
   hipError_t e;
   const int ns = split_parts(an.compute);
   if (ns && L.kind == PlainLaunch::kMain) {
-    e = p->index_bits == 32 ? launch_split(make_args<uint32_t>(p, x, y, C, alpha, beta), L, ns, s)
-                            : launch_split(make_args<int64_t>(p, x, y, C, alpha, beta), L, ns, s);
+    if (p->index_bits == 32) {
+      PlainArgs<uint32_t> a = make_args<uint32_t>(p, x, y, C, alpha, beta);
+      if (xp) {  // the packed buffer is addressed from its start, not through offsets
+        a.x = x;
+        a.x_nkb = (int32_t)((an.K + L.bk - 1) / L.bk);
+      }
+      if (yp) {
+        a.y = y;
+        a.y_nkb = (int32_t)((an.K + L.bk - 1) / L.bk);
+      }
+      e = launch_split(a, L, ns, s);
+    } else {
+      e = launch_split(make_args<int64_t>(p, x, y, C, alpha, beta), L, ns, s);
+    }
+  } else if (p->index_bits == 32) {
+    PlainArgs<uint32_t> a = make_args<uint32_t>(p, x, y, C, alpha, beta);
+    if (xp) {
+      a.x = x;
+      a.x_nkb = (int32_t)((an.K + L.bk - 1) / L.bk);
+    }
+    if (yp) {
+      a.y = y;
+      a.y_nkb = (int32_t)((an.K + L.bk - 1) / L.bk);
+    }
+    e = launch_plain(an.dtype, a, L, s);
   } else {
-    e = p->index_bits == 32 ? launch_plain(an.dtype, make_args<uint32_t>(p, x, y, C, alpha, beta), L, s)
-                            : launch_plain(an.dtype, make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
+    e = launch_plain(an.dtype, make_args<int64_t>(p, x, y, C, alpha, beta), L, s);
   }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return FAMLIES_OK;
+}
+
+famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+                               void* C, void* stream) {
+  return execute_impl(p, alpha, A, B, beta, C, 0, stream);
+}
+
+famlies_status famlies_execute_packed(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+                                      void* C, int packed, void* stream) {
+  if (packed < 0 || packed > 3) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute_packed: packed must be 0..3");
+  return execute_impl(p, alpha, A, B, beta, C, packed, stream);
 }
 
 }  // extern "C"

@@ -23,6 +23,7 @@ struct PlainArgs {
   const int64_t* yl;
   const int64_t* cl;
   int32_t M, N, K, L;
+  int32_t x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y (0: not packed)
   int32_t tiles_m, tiles_n, splits, kchunk;
   double alpha, beta;
   void* work;       // split-K partials [splits][tiles_m*BM][tiles_n*BN]

@@ -61,7 +61,7 @@ __host__ __device__ constexpr int batch_class_tile(int cls) { return cls == 0 ? 
 template <typename T, int BT, bool XK, bool YK>
 __device__ __forceinline__ void run_item(const TileJob<uint32_t>& j, T* smem) {
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
-  PlainTile<T, BT, BT, BK, XK, YK>::template run<uint32_t>(j, smem);
+  PlainTile<T, BT, BT, BK, XK ? kKGather : kRowGather, YK ? kKGather : kRowGather>::template run<uint32_t>(j, smem);
 }
 
 template <typename T>
@@ -99,6 +99,7 @@ __global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
     j.beta = a.beta;
     j.work = nullptr;
     j.ldw = 0;
+    j.x_nkb = j.y_nkb = 0;
     switch (((flags >> 1) & 3) | (cls << 2)) {
       case 0: run_item<T, 64, false, false>(j, smem); break;
       case 1: run_item<T, 64, true, false>(j, smem); break;

@@ -169,4 +169,50 @@ struct TileGather {
   }
 };
 
+// Loader for a pre-packed operand (the packing step hoisted out of repeated
+// calls: Girder 2, "Enabling optimizations across layers").  The packed
+// buffer holds the operand tile by tile in the kernel's order: block
+// (tile, kb) is BR x BK elements stored [row][k] densely, zero-filled past the
+// problem edges, blocks ordered tile-major (tile * nkb + kb).  A slice is then
+// a contiguous run of 16-byte vectors: no indexing vectors, no edge tests.
+template <typename T, int BR, int BK>
+struct PackedGather {
+  static constexpr int VK = 16 / (int)sizeof(T);
+  static constexpr int LDK = BK + VK;
+  static constexpr int NV = BR * BK / VK;  // vectors per block
+  static constexpr int VPT = NV / kThreads;
+  static_assert(NV % kThreads == 0 && BK % VK == 0, "packed block does not divide the workgroup");
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  vec_t v[VPT];
+  int tile = 0, kb = 0, nkb = 1, tid = 0;
+
+  template <typename OffT>
+  __device__ __forceinline__ void init(const OffT* /*unused*/, int tile_r0, int t) {
+    tile = tile_r0 / BR;
+    tid = t;
+  }
+  template <typename OffT>
+  __device__ __forceinline__ void fetch_k(const OffT* /*unused*/, int k0) {
+    kb = k0 / BK;
+  }
+  __device__ __forceinline__ void load(const T* __restrict__ base) {
+    const vec_t* blk = reinterpret_cast<const vec_t*>(base + ((size_t)tile * nkb + kb) * (size_t)(BR * BK));
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) v[q] = blk[tid + q * kThreads];
+  }
+  __device__ __forceinline__ void store(T* __restrict__ lds, int /*k0*/, int /*kend*/) const {
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int e = (tid + q * kThreads) * VK;
+      *reinterpret_cast<vec_t*>(lds + (e / BK) * LDK + e % BK) = v[q];
+    }
+  }
+};
+
+// Operand loaders by mode: 0 row-gathered, 1 K-gathered, 2 pre-packed.
+enum { kRowGather = 0, kKGather = 1, kPacked = 2 };
+template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1>
+using Loader = typename std::conditional<MODE == kPacked, PackedGather<T, BR, BK>,
+                                         TileGather<T, OffT, BR, BK, MODE == kKGather, KV>>::type;
+
 }  // namespace famlies

@@ -11,7 +11,7 @@ namespace famlies {
 struct PlainLaunch {
   enum Kind { kMain = 0, kScale = 1 } kind = kMain;
   int bm = 128, bn = 128, bk = 16;
-  bool xk = true, yk = true;
+  int xm = 1, ym = 1;  // operand loader modes: 0 row-gathered, 1 K-gathered, 2 pre-packed
 };
 
 hipError_t launch_plain(int dtype, const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s);

@@ -20,9 +20,9 @@
 
 namespace famlies {
 
-template <typename T, typename OffT, int BM, int BN, int BK, bool XK, bool YK>
+template <typename T, typename OffT, int BM, int BN, int BK, int XM, int YM>
 __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_contract(PlainArgs<OffT> a) {
-  using Tile = PlainTile<T, BM, BN, BK, XK, YK>;
+  using Tile = PlainTile<T, BM, BN, BK, XM, YM>;
   __shared__ T smem[Tile::SMEM];
   const int lid0 = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_m * a.tiles_n;
@@ -33,8 +33,13 @@ __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_co
   const int t = lid % ntiles;
   const int pm = t % a.tiles_m, pn = t / a.tiles_m;  // M fastest: neighbours share Y's panel
   TileJob<OffT> j;
-  j.x = static_cast<const T*>(a.x) + a.xl[l];
-  j.y = static_cast<const T*>(a.y) + a.yl[l];
+  // a pre-packed operand holds its batch planes back to back
+  j.x = static_cast<const T*>(a.x) +
+        (XM == kPacked ? (int64_t)l * a.tiles_m * a.x_nkb * (int64_t)(BM * BK) : a.xl[l]);
+  j.y = static_cast<const T*>(a.y) +
+        (YM == kPacked ? (int64_t)l * a.tiles_n * a.y_nkb * (int64_t)(BN * BK) : a.yl[l]);
+  j.x_nkb = a.x_nkb;
+  j.y_nkb = a.y_nkb;
   j.c = static_cast<T*>(a.c) + a.cl[l];
   j.xmn = a.xmn;
   j.xk = a.xk;
@@ -90,17 +95,34 @@ __global__ __launch_bounds__(kThreads) void scale_c(PlainArgs<OffT> a) {
 }
 
 // ------------------------------------------------------------------ dispatch
+template <typename T, typename OffT, int BM, int BN, int BK, int XM, int YM>
+static void launch_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, XM, YM>), dim3(grid), dim3(kThreads), 0, s, a);
+}
+
+// Gathered operands (modes 0, 1) for every tile; pre-packed operands (mode 2)
+// for the 128 x 128 tile with 32-bit offsets only.
 template <typename T, typename OffT, int BM, int BN, int BK>
-static hipError_t launch_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int grid, hipStream_t s) {
-  if (xk && yk)
-    hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, true, true>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (xk)
-    hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, true, false>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (yk)
-    hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, false, true>), dim3(grid), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, false, false>), dim3(grid), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
+static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
+  const int code = xm * 3 + ym;
+  switch (code) {
+    case 0: launch_one<T, OffT, BM, BN, BK, 0, 0>(a, grid, s); return hipGetLastError();
+    case 1: launch_one<T, OffT, BM, BN, BK, 0, 1>(a, grid, s); return hipGetLastError();
+    case 3: launch_one<T, OffT, BM, BN, BK, 1, 0>(a, grid, s); return hipGetLastError();
+    case 4: launch_one<T, OffT, BM, BN, BK, 1, 1>(a, grid, s); return hipGetLastError();
+    default: break;
+  }
+  if constexpr (BM == 128 && BN == 128 && sizeof(OffT) == 4) {
+    switch (code) {
+      case 2: launch_one<T, OffT, BM, BN, BK, 0, 2>(a, grid, s); return hipGetLastError();
+      case 5: launch_one<T, OffT, BM, BN, BK, 1, 2>(a, grid, s); return hipGetLastError();
+      case 6: launch_one<T, OffT, BM, BN, BK, 2, 0>(a, grid, s); return hipGetLastError();
+      case 7: launch_one<T, OffT, BM, BN, BK, 2, 1>(a, grid, s); return hipGetLastError();
+      case 8: launch_one<T, OffT, BM, BN, BK, 2, 2>(a, grid, s); return hipGetLastError();
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, typename OffT>
@@ -116,9 +138,9 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
   hipError_t e = hipErrorInvalidValue;
   if (L.bm == 128 && L.bn == 128 && L.bk == BK)
-    e = launch_tile<T, OffT, 128, 128, BK>(a, L.xk, L.yk, grid, s);
+    e = launch_tile<T, OffT, 128, 128, BK>(a, L.xm, L.ym, grid, s);
   else if (L.bm == 64 && L.bn == 64 && L.bk == BK)
-    e = launch_tile<T, OffT, 64, 64, BK>(a, L.xk, L.yk, grid, s);
+    e = launch_tile<T, OffT, 64, 64, BK>(a, L.xm, L.ym, grid, s);
   if (e != hipSuccess || a.splits == 1) return e;
   hipLaunchKernelGGL((splitk_reduce<T, OffT>), dim3(eg), dim3(kThreads), 0, s, a, a.tiles_n * L.bn,
                      a.tiles_m * L.bm);

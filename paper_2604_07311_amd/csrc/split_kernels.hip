@@ -76,13 +76,61 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
   }
 }
 
+// Operand loader of the split kernels: a gathered FP32 slice split at the
+// LDS store (modes kRowGather, kKGather), or pre-packed bf16 parts copied as
+// they are (kPacked: block (tile, kb) holds the NS part planes of BR x BK
+// bf16, [row][k], zero-filled past the edges; see famlies_pack).
+template <typename OffT, int BR, int NS, int MODE>
+struct SplitLoader {
+  static constexpr bool KF = MODE == kKGather;
+  using G = TileGather<float, OffT, BR, kB3K, KF, KF ? 2 : 1>;
+  G g;
+  int nkb = 0;
+  __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
+  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
+  __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
+  __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int k0, int kend) const {
+    store_split<NS, G, KF>(g, tiles, tile_elems, k0, kend);
+  }
+};
+
+template <typename OffT, int BR, int NS>
+struct SplitLoader<OffT, BR, NS, kPacked> {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  static constexpr int VPT = BR * kB3K / 8 / kThreads;  // 16-byte vectors per thread and part
+  static_assert(VPT >= 1, "packed block does not divide the workgroup");
+  u32x4 v[NS][VPT];
+  int tile = 0, kb = 0, nkb = 1, tid = 0;
+  __device__ __forceinline__ void init(const OffT*, int tile_r0, int t) {
+    tile = tile_r0 / BR;
+    tid = t;
+  }
+  __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb = k0 / kB3K; }
+  __device__ __forceinline__ void load(const void* base) {
+    const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb) * (size_t)(NS * BR * kB3K);
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) v[t][q] = reinterpret_cast<const u32x4*>(blk + t * BR * kB3K)[tid + q * kThreads];
+  }
+  __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+#pragma unroll
+      for (int q = 0; q < VPT; ++q) {
+        const int e = (tid + q * kThreads) * 8;
+        *reinterpret_cast<u32x4*>(tiles + t * tile_elems + (e / kB3K) * kB3LD + e % kB3K) = v[t][q];
+      }
+  }
+};
+
 // One workgroup: a BM x BN tile of C, 2 x 2 waves of (BM/2) x (BN/2), each
 // made of 32 x 32 MFMA blocks.
-template <typename OffT, int BM, int BN, bool XK, bool YK, int NS>
+template <typename OffT, int BM, int BN, int XM, int YM, int NS>
 __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   constexpr int BK = kB3K;
-  using GX = TileGather<float, OffT, BM, BK, XK, XK ? 2 : 1>;
-  using GY = TileGather<float, OffT, BN, BK, YK, YK ? 2 : 1>;
+  using GX = SplitLoader<OffT, BM, NS, XM>;
+  using GY = SplitLoader<OffT, BN, NS, YM>;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
   constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per part tile
@@ -104,13 +152,20 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   const int kbeg = split * a.kchunk;
   const int kend = min(a.K, kbeg + a.kchunk);
   const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
-  const float* __restrict__ X = static_cast<const float*>(a.x) + a.xl[l];
-  const float* __restrict__ Y = static_cast<const float*>(a.y) + a.yl[l];
+  // a pre-packed operand holds its batch planes back to back
+  const void* X = XM == kPacked ? static_cast<const void*>(static_cast<const __bf16*>(a.x) +
+                                                           (int64_t)l * a.tiles_m * a.x_nkb * (int64_t)(NS * BM * BK))
+                                : static_cast<const void*>(static_cast<const float*>(a.x) + a.xl[l]);
+  const void* Y = YM == kPacked ? static_cast<const void*>(static_cast<const __bf16*>(a.y) +
+                                                           (int64_t)l * a.tiles_n * a.y_nkb * (int64_t)(NS * BN * BK))
+                                : static_cast<const void*>(static_cast<const float*>(a.y) + a.yl[l]);
 
   GX gx;
   GY gy;
   gx.init(a.xmn, m0, tid);
   gy.init(a.ymn, n0, tid);
+  gx.nkb = a.x_nkb;
+  gy.nkb = a.y_nkb;
 
   f32x16 acc[NS][MB][NB];  // acc[o]: products whose parts' orders sum to o
 #pragma unroll
@@ -123,8 +178,8 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   const int g = lane / 32, r = lane % 32;
   auto stage_store = [&](int buf, int k0) {
     __bf16* base = smem + buf * STAGE;
-    store_split<NS, GX, XK>(gx, base, XS, k0, kend);
-    store_split<NS, GY, YK>(gy, base + NS * XS, YS, k0, kend);
+    gx.store(base, XS, k0, kend);
+    gy.store(base + NS * XS, YS, k0, kend);
   };
   if (nk > 0) {
     gx.fetch_k(a.xk, kbeg);
@@ -235,17 +290,34 @@ __global__ __launch_bounds__(kThreads) void split_reduce(PlainArgs<OffT> a, int 
   *cp = (float)v;
 }
 
+template <typename OffT, int BM, int BN, int NS, int XM, int YM>
+static void launch_split_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((split_contract<OffT, BM, BN, XM, YM, NS>), dim3(grid), dim3(kThreads), 0, s, a);
+}
+
+// Gathered operands for every tile; pre-packed operands for the 128 x 128 and
+// 256 x 128 tiles with 32-bit offsets only.
 template <typename OffT, int BM, int BN, int NS>
-static hipError_t launch_split_tile(const PlainArgs<OffT>& a, bool xk, bool yk, int grid, hipStream_t s) {
-  if (xk && yk)
-    hipLaunchKernelGGL((split_contract<OffT, BM, BN, true, true, NS>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (xk)
-    hipLaunchKernelGGL((split_contract<OffT, BM, BN, true, false, NS>), dim3(grid), dim3(kThreads), 0, s, a);
-  else if (yk)
-    hipLaunchKernelGGL((split_contract<OffT, BM, BN, false, true, NS>), dim3(grid), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((split_contract<OffT, BM, BN, false, false, NS>), dim3(grid), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
+static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
+  const int code = xm * 3 + ym;
+  switch (code) {
+    case 0: launch_split_one<OffT, BM, BN, NS, 0, 0>(a, grid, s); return hipGetLastError();
+    case 1: launch_split_one<OffT, BM, BN, NS, 0, 1>(a, grid, s); return hipGetLastError();
+    case 3: launch_split_one<OffT, BM, BN, NS, 1, 0>(a, grid, s); return hipGetLastError();
+    case 4: launch_split_one<OffT, BM, BN, NS, 1, 1>(a, grid, s); return hipGetLastError();
+    default: break;
+  }
+  if constexpr (BM >= 128 && BN == 128 && sizeof(OffT) == 4) {
+    switch (code) {
+      case 2: launch_split_one<OffT, BM, BN, NS, 0, 2>(a, grid, s); return hipGetLastError();
+      case 5: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();
+      case 6: launch_split_one<OffT, BM, BN, NS, 2, 0>(a, grid, s); return hipGetLastError();
+      case 7: launch_split_one<OffT, BM, BN, NS, 2, 1>(a, grid, s); return hipGetLastError();
+      case 8: launch_split_one<OffT, BM, BN, NS, 2, 2>(a, grid, s); return hipGetLastError();
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename OffT>
@@ -254,16 +326,16 @@ static hipError_t launch_split_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   hipError_t e = hipErrorInvalidValue;
   if (ns == 2) {
     if (L.bm == 256 && L.bn == 128)
-      e = launch_split_tile<OffT, 256, 128, 2>(a, L.xk, L.yk, grid, s);
+      e = launch_split_tile<OffT, 256, 128, 2>(a, L.xm, L.ym, grid, s);
     else if (L.bm == 128 && L.bn == 128)
-      e = launch_split_tile<OffT, 128, 128, 2>(a, L.xk, L.yk, grid, s);
+      e = launch_split_tile<OffT, 128, 128, 2>(a, L.xm, L.ym, grid, s);
     else if (L.bm == 64 && L.bn == 64)
-      e = launch_split_tile<OffT, 64, 64, 2>(a, L.xk, L.yk, grid, s);
+      e = launch_split_tile<OffT, 64, 64, 2>(a, L.xm, L.ym, grid, s);
   } else if (ns == 3) {
     if (L.bm == 128 && L.bn == 128)
-      e = launch_split_tile<OffT, 128, 128, 3>(a, L.xk, L.yk, grid, s);
+      e = launch_split_tile<OffT, 128, 128, 3>(a, L.xm, L.ym, grid, s);
     else if (L.bm == 64 && L.bn == 64)
-      e = launch_split_tile<OffT, 64, 64, 3>(a, L.xk, L.yk, grid, s);
+      e = launch_split_tile<OffT, 64, 64, 3>(a, L.xm, L.ym, grid, s);
   }
   if (e != hipSuccess || a.splits == 1) return e;
   const int64_t mn = (int64_t)a.M * a.N;

@@ -26,15 +26,17 @@ struct TileJob {
   double alpha, beta;
   void* work;  // non-null: write partial sums here, dense [m][n] with leading dim ldw
   int ldw;
+  int x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y
 };
 
-template <typename T, int BM, int BN, int BK, bool XK, bool YK>
+// XM, YM: operand loader modes (kRowGather, kKGather, kPacked).
+template <typename T, int BM, int BN, int BK, int XM, int YM>
 struct PlainTile {
   using MF = Mfma<T>;
   template <typename OffT>
-  using GX = TileGather<T, OffT, BM, BK, XK>;
+  using GX = Loader<T, OffT, BM, BK, XM>;
   template <typename OffT>
-  using GY = TileGather<T, OffT, BN, BK, YK>;
+  using GY = Loader<T, OffT, BN, BK, YM>;
   static constexpr int LX = GX<int32_t>::LDK;
   static constexpr int LY = GY<int32_t>::LDK;
   static constexpr int XS = BM * LX, YS = BN * LY;
@@ -57,6 +59,8 @@ struct PlainTile {
     GY<OffT> gy;
     gx.init(j.xmn, j.m0, tid);
     gy.init(j.ymn, j.n0, tid);
+    if constexpr (XM == kPacked) gx.nkb = j.x_nkb;
+    if constexpr (YM == kPacked) gy.nkb = j.y_nkb;
 
     typename MF::Acc acc[MB][NB];
 #pragma unroll
