@@ -190,6 +190,33 @@ famlies_status famlies_pack(famlies_plan p, int operand, const void *src, void *
 famlies_status famlies_execute_packed(famlies_plan p, double alpha, const void *A, const void *B,
                                       double beta, void *C, int packed, void *stream);
 
+/* Contraction networks: an ordered sequence of contractions over tensors
+ * that are either bound by the caller or intermediates owned by the network
+ * (sequences of contractions, Girder 5; packing hoisted out of repeated
+ * calls, Girder 2).  Build: famlies_network_add_tensor (descriptor; an
+ * intermediate gets a zeroed device allocation of its address span at
+ * compile time), famlies_network_add_contraction (tensor ids; flags may ask
+ * to keep A and/or B pre-packed: a bound operand is packed on the first run
+ * after each bind, an intermediate on every run), famlies_network_compile
+ * (plans every step).  famlies_network_bind sets a caller tensor's base
+ * pointer; famlies_network_execute runs the steps in order on `stream`
+ * (after the first run per binding it allocates nothing and does not
+ * synchronise).  famlies_network_tensor_ptr returns a tensor's base pointer
+ * (an intermediate's after compile). */
+typedef struct famlies_network_s *famlies_network;
+#define FAMLIES_NET_PACK_A 1
+#define FAMLIES_NET_PACK_B 2
+famlies_status famlies_network_create(famlies_handle h, famlies_network *out, int dtype, int compute);
+famlies_status famlies_network_add_tensor(famlies_network n, const famlies_tensor *desc, int intermediate,
+                                          int32_t *id);
+famlies_status famlies_network_add_contraction(famlies_network n, double alpha, int32_t a, int32_t b,
+                                               double beta, int32_t c, int flags);
+famlies_status famlies_network_compile(famlies_network n);
+famlies_status famlies_network_bind(famlies_network n, int32_t id, void *ptr);
+famlies_status famlies_network_tensor_ptr(famlies_network n, int32_t id, void **ptr);
+famlies_status famlies_network_execute(famlies_network n, void *stream);
+famlies_status famlies_network_destroy(famlies_network n);
+
 /* Autotune: time the candidate tile shapes on synthetic problems of each
  * size class on the handle's device and write the table to table_path
  * (text, one line per class); the handle then uses it.  flags: bit 0 = quick

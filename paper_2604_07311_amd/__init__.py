@@ -75,7 +75,12 @@ EXPORTS = [
     "famlies_plan_destroy", "famlies_plan_get_info", "famlies_analyze", "famlies_batch_plan",
     "famlies_batch_execute", "famlies_tune", "famlies_load_tune_table", "famlies_last_error",
     "famlies_version", "famlies_pack_size", "famlies_pack", "famlies_execute_packed",
+    "famlies_network_create", "famlies_network_add_tensor", "famlies_network_add_contraction",
+    "famlies_network_compile", "famlies_network_bind", "famlies_network_tensor_ptr",
+    "famlies_network_execute", "famlies_network_destroy",
 ]
+FAMLIES_NET_PACK_A = 1
+FAMLIES_NET_PACK_B = 2
 
 
 class FamliesError(RuntimeError):
@@ -116,6 +121,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "famlies_pack_size": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
             "famlies_pack": ([vp, i32, vp, vp, vp], i32),
             "famlies_execute_packed": ([vp, dbl, vp, vp, dbl, vp, i32, vp], i32),
+            "famlies_network_create": ([vp, ctypes.POINTER(vp), i32, i32], i32),
+            "famlies_network_add_tensor": ([vp, T, i32, ctypes.POINTER(ctypes.c_int32)], i32),
+            "famlies_network_add_contraction": ([vp, dbl, i32, i32, dbl, i32, i32], i32),
+            "famlies_network_compile": ([vp], i32),
+            "famlies_network_bind": ([vp, i32, vp], i32),
+            "famlies_network_tensor_ptr": ([vp, i32, ctypes.POINTER(vp)], i32),
+            "famlies_network_execute": ([vp, vp], i32),
+            "famlies_network_destroy": ([vp], i32),
             "famlies_last_error": ([], ctypes.c_char_p),
             "famlies_version": ([], ctypes.c_char_p),
         }
@@ -195,6 +208,56 @@ def famlies_execute_packed(plan: int, alpha: float, A_ptr: int, B_ptr: int, beta
                            packed: int, stream: int = 0) -> None:
     _check(load_library().famlies_execute_packed(plan, float(alpha), A_ptr, B_ptr, float(beta), C_ptr,
                                                  int(packed), stream), "famlies_execute_packed")
+
+
+class Network:
+    """Thin wrapper over the famlies_network_* calls (same names underneath).
+
+    >>> net = Network(FAMLIES_F64)
+    >>> w = net.tensor(W.shape, W.stride(), "abef")          # bound by the caller
+    >>> i1 = net.tensor(shape, strides, "abij", intermediate=True)
+    >>> net.contract(1.0, w, t, 0.0, i1, pack_a=True)
+    >>> net.compile(); net.bind(w, W.data_ptr()); net.execute(stream)
+    """
+
+    def __init__(self, dtype: int, compute: int = FAMLIES_NATIVE, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.famlies_network_create(handle(device), ctypes.byref(h), dtype, compute),
+               "famlies_network_create")
+        self.ptr = h.value
+
+    def tensor(self, extents, strides, labels, intermediate: bool = False) -> int:
+        i = ctypes.c_int32()
+        d = make_desc(extents, strides, labels)
+        _check(load_library().famlies_network_add_tensor(self.ptr, ctypes.byref(d), int(intermediate),
+                                                         ctypes.byref(i)), "famlies_network_add_tensor")
+        return i.value
+
+    def contract(self, alpha, a: int, b: int, beta, c: int, pack_a: bool = False, pack_b: bool = False):
+        flags = (FAMLIES_NET_PACK_A if pack_a else 0) | (FAMLIES_NET_PACK_B if pack_b else 0)
+        _check(load_library().famlies_network_add_contraction(self.ptr, float(alpha), a, b, float(beta), c,
+                                                              flags), "famlies_network_add_contraction")
+
+    def compile(self):
+        _check(load_library().famlies_network_compile(self.ptr), "famlies_network_compile")
+
+    def bind(self, tid: int, ptr: int):
+        _check(load_library().famlies_network_bind(self.ptr, tid, ptr), "famlies_network_bind")
+
+    def tensor_ptr(self, tid: int) -> int:
+        q = ctypes.c_void_p()
+        _check(load_library().famlies_network_tensor_ptr(self.ptr, tid, ctypes.byref(q)),
+               "famlies_network_tensor_ptr")
+        return q.value
+
+    def execute(self, stream: int = 0):
+        _check(load_library().famlies_network_execute(self.ptr, stream), "famlies_network_execute")
+
+    def close(self):
+        if self.ptr:
+            _check(load_library().famlies_network_destroy(self.ptr), "famlies_network_destroy")
+            self.ptr = None
 
 
 def famlies_plan_destroy(plan: int) -> None:
@@ -366,4 +429,4 @@ def contract(alpha: float, A, la, B, lb, beta: float = 0.0, C=None, lc=None, *,
 from .autograd import ContractFn, contract_ad  # noqa: E402
 
 __all__ = [n for n in EXPORTS] + ["contract", "ContractFn", "contract_ad", "make_desc",
-                                  "load_library", "FamliesError", "plan_for"]
+                                  "load_library", "FamliesError", "plan_for", "Network"]
