@@ -181,8 +181,8 @@ famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta,
  * split into bf16 parts -- so that famlies_execute_packed copies whole tiles
  * instead of gathering and splitting.  dst must hold famlies_pack_size bytes
  * and be 16-byte aligned; it is owned by the caller and valid for this plan
- * only.  UNSUPPORTED for plans whose tile is not 128 x 128 (256 x 128 also for
- * bf16x3) or whose offsets need 64 bits.  Asynchronous on `stream`. */
+ * only.  UNSUPPORTED for plans whose offsets need 64 bits (an operand
+ * spanning 4 GiB or more).  Asynchronous on `stream`. */
 famlies_status famlies_pack_size(famlies_plan p, int operand, size_t *bytes);
 famlies_status famlies_pack(famlies_plan p, int operand, const void *src, void *dst, void *stream);
 /* As famlies_execute, where bit 0 of `packed` says A points to a buffer

@@ -7,6 +7,7 @@
 // back.  For the split-bf16 modes each block holds the NS bf16 part planes of
 // the split that the kernels would otherwise do while staging.
 #include "device.hpp"
+#include "launch.hpp"
 #include "runtime.hpp"
 
 namespace famlies {
@@ -74,17 +75,26 @@ static hipError_t launch_pack_t(const PackArgs<OffT>& a, int dtype, int ns, int 
   if (ns == 0) {
     if (dtype == FAMLIES_F64 && br == 128 && bk == 16)
       hipLaunchKernelGGL((pack_plain<double, OffT, 128, 16>), dim3(grid), dim3(kThreads), 0, s, a);
+    else if (dtype == FAMLIES_F64 && br == 64 && bk == 16)
+      hipLaunchKernelGGL((pack_plain<double, OffT, 64, 16>), dim3(grid), dim3(kThreads), 0, s, a);
     else if (dtype == FAMLIES_F32 && br == 128 && bk == 32)
       hipLaunchKernelGGL((pack_plain<float, OffT, 128, 32>), dim3(grid), dim3(kThreads), 0, s, a);
+    else if (dtype == FAMLIES_F32 && br == 64 && bk == 32)
+      hipLaunchKernelGGL((pack_plain<float, OffT, 64, 32>), dim3(grid), dim3(kThreads), 0, s, a);
     else
       return hipErrorInvalidValue;
-  } else if (bk == 32 && br == 128) {
-    if (ns == 2)
-      hipLaunchKernelGGL((pack_split<OffT, 128, 2>), dim3(grid), dim3(kThreads), 0, s, a);
-    else
-      hipLaunchKernelGGL((pack_split<OffT, 128, 3>), dim3(grid), dim3(kThreads), 0, s, a);
-  } else if (bk == 32 && br == 256 && ns == 2) {
+  } else if (bk != 32) {
+    return hipErrorInvalidValue;
+  } else if (ns == 2 && br == 256) {
     hipLaunchKernelGGL((pack_split<OffT, 256, 2>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (ns == 2 && br == 128) {
+    hipLaunchKernelGGL((pack_split<OffT, 128, 2>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (ns == 2 && br == 64) {
+    hipLaunchKernelGGL((pack_split<OffT, 64, 2>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (ns == 3 && br == 128) {
+    hipLaunchKernelGGL((pack_split<OffT, 128, 3>), dim3(grid), dim3(kThreads), 0, s, a);
+  } else if (ns == 3 && br == 64) {
+    hipLaunchKernelGGL((pack_split<OffT, 64, 3>), dim3(grid), dim3(kThreads), 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }
@@ -118,10 +128,10 @@ famlies_status pack_geom(famlies_plan p, int operand, PackGeom* g) {
   g->x = (operand == 0) != an.swapped;
   g->br = g->x ? p->cfg.bm : p->cfg.bn;
   g->bk = p->cfg.bk;
-  const bool tile_ok = ns ? (p->cfg.bn == 128 && (p->cfg.bm == 128 || (p->cfg.bm == 256 && ns == 2)))
-                          : (p->cfg.bm == 128 && p->cfg.bn == 128);
+  const bool tile_ok = ns ? split_tile_supported(ns, p->cfg.bm, p->cfg.bn)
+                          : plain_tile_supported(an.dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk);
   if (!tile_ok || p->index_bits != 32)
-    return fail(FAMLIES_ERR_UNSUPPORTED, "pack: this plan's tile shape or offset width has no packed kernel");
+    return fail(FAMLIES_ERR_UNSUPPORTED, "pack: this plan's offsets need 64 bits (no packed kernel)");
   if (an.M == 0 || an.N == 0 || an.K == 0) return fail(FAMLIES_ERR_UNSUPPORTED, "pack: empty problem");
   g->rows = g->x ? an.M : an.N;
   g->tiles = (g->rows + g->br - 1) / g->br;

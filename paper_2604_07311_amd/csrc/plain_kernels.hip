@@ -100,8 +100,8 @@ static void launch_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, XM, YM>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered operands (modes 0, 1) for every tile; pre-packed operands (mode 2)
-// for the 128 x 128 tile with 32-bit offsets only.
+// Gathered operands (modes 0, 1) with either offset width; pre-packed
+// operands (mode 2) with 32-bit offsets only.
 template <typename T, typename OffT, int BM, int BN, int BK>
 static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
   const int code = xm * 3 + ym;
@@ -112,7 +112,7 @@ static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid
     case 4: launch_one<T, OffT, BM, BN, BK, 1, 1>(a, grid, s); return hipGetLastError();
     default: break;
   }
-  if constexpr (BM == 128 && BN == 128 && sizeof(OffT) == 4) {
+  if constexpr (sizeof(OffT) == 4) {
     switch (code) {
       case 2: launch_one<T, OffT, BM, BN, BK, 0, 2>(a, grid, s); return hipGetLastError();
       case 5: launch_one<T, OffT, BM, BN, BK, 1, 2>(a, grid, s); return hipGetLastError();

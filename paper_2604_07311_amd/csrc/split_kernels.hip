@@ -295,8 +295,8 @@ static void launch_split_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) 
   hipLaunchKernelGGL((split_contract<OffT, BM, BN, XM, YM, NS>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered operands for every tile; pre-packed operands for the 128 x 128 and
-// 256 x 128 tiles with 32-bit offsets only.
+// Gathered operands with either offset width; pre-packed operands with
+// 32-bit offsets only.
 template <typename OffT, int BM, int BN, int NS>
 static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
   const int code = xm * 3 + ym;
@@ -307,7 +307,7 @@ static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, in
     case 4: launch_split_one<OffT, BM, BN, NS, 1, 1>(a, grid, s); return hipGetLastError();
     default: break;
   }
-  if constexpr (BM >= 128 && BN == 128 && sizeof(OffT) == 4) {
+  if constexpr (sizeof(OffT) == 4) {
     switch (code) {
       case 2: launch_split_one<OffT, BM, BN, NS, 0, 2>(a, grid, s); return hipGetLastError();
       case 5: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();

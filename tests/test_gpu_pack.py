@@ -121,13 +121,24 @@ def test_packed_split_k_and_batch_modes(gpu, tmp_path, dtype, compute):
     fm.famlies_destroy(h)
 
 
-def test_pack_rejects_unsupported_plans(gpu):
+@pytest.mark.parametrize("dtype,compute", [("f64", "native"), ("f32", "native"), ("f32", "bf16x3"),
+                                           ("f32", "bf16x6")])
+def test_packed_small_tiles(gpu, dtype, compute):
+    """Small problems plan 64 x 64 tiles (and split-K); packed equals gathered."""
+    p = round_inputs(synth.plain16(seed=99, n=9, dist="uniform"), dtype)
+    h = gpu.fm.handle(0)
+    info, gathered, packed = _run(gpu, h, p, dtype, compute, 3)
+    note("small packed %s %s tile %d split %d" % (dtype, compute, info["tile_m"], info["split_k"]))
+    np.testing.assert_array_equal(packed, gathered)
+
+
+def test_pack_rejects_bad_arguments(gpu):
     fm = gpu.fm
-    p = synth.plain16(seed=98, n=6)   # small: planned with 64 x 64 tiles
+    p = synth.plain16(seed=98, n=6)
     plan = gpu.plan(p, "f64")
     with pytest.raises(fm.FamliesError) as e:
-        fm.famlies_pack_size(plan, 0)
-    assert e.value.code == fm.FAMLIES_ERR_UNSUPPORTED
+        fm.famlies_pack_size(plan, 2)
+    assert e.value.code == fm.FAMLIES_ERR_INVALID_ARG
     with pytest.raises(fm.FamliesError) as e:
         fm.famlies_execute_packed(plan, 1.0, 0, 0, 0.0, 0, 7, 0)
     assert e.value.code == fm.FAMLIES_ERR_INVALID_ARG
