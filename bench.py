@@ -208,10 +208,39 @@ def cpu_baseline(p, target_s=12.0):
                       % (n, p.name, K, t)}
 
 
-def roofline(flops, launch_ms, peak, bound="mfma"):
+# HBM bytes per launch of a workload's dominant kernel, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE: KiB per dispatch), each scaled by
+# the ratio the same counter shows for a plain device copy of 1 GiB taken in
+# the same run.  A record holds only for the kernel sources it was measured
+# on (`sources` = kernel_sources_sha() then); after any change to them the
+# traffic is reported as null until the counters are taken again.
+TRAFFIC = {}
+
+
+def kernel_sources_sha():
+    import hashlib
+    d = os.path.join(ROOT, "paper_2604_07311_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic(key):
+    rec = TRAFFIC.get(key)
+    if rec is None or rec["sources"] != kernel_sources_sha():
+        return None
+    return int(round(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])))
+
+
+def roofline(flops, launch_ms, peak, bound="mfma", key=None):
     achieved = flops / (launch_ms * 1e-3) / 1e12
     return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1),
-            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4), "traffic": None}
+            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
+            "traffic": traffic(key) if key else None}
 
 
 def base_record(args, value, ms, dtype, config, unit="GFLOP/s"):
@@ -255,7 +284,7 @@ def wl_ladder(args):
                        "split_k": r["info"]["split_k"]})
     out["pct_mfma_peak"] = round(100 * flops / (r["ms"] * 1e-3) / PEAK[head], 2)
     out["error_vs_fp64"] = r["check"]
-    out["roofline"] = roofline(flops, r["launch"], PEAK[head])
+    out["roofline"] = roofline(flops, r["launch"], PEAK[head], key=("ladder", head, args.v, args.o))
     if "packed_W" in r:
         out["packed_W"] = r["packed_W"]
     for dt, rr in res.items():
@@ -265,7 +294,7 @@ def wl_ladder(args):
         out.setdefault("secondary", {})[dt] = {
             "value": round(v / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(rr["ms"], 4),
             "pct_mfma_peak": round(100 * v / PEAK[dt], 2), "error_vs_fp64": rr["check"],
-            "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt])}
+            "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt], key=("ladder", dt, args.v, args.o))}
         if "packed_W" in rr:
             out["secondary"][dt]["packed_W"] = rr["packed_W"]
     if not args.no_cpu_baseline:

@@ -10,7 +10,9 @@ Both gradients are themselves labelled contractions, so they run on the
 same planner and kernels as the forward (the paper's aim of one engine
 reused across operations, Section "Building on important advances", BLIS
 2.0 building blocks; ML use of tensor operations, "Project Motivation").
-The Function is functional: it never writes into C0.
+The Function is functional: it never writes into C0.  Gradients take their
+input's strides when that input is dense (torch's preserve_format), so the
+engine accumulates them without a layout copy.
 """
 from __future__ import annotations
 
@@ -37,10 +39,10 @@ class ContractFn(torch.autograd.Function):
         alpha, la, lb, beta, lc, compute, has_c0 = ctx.cfg
         dA = dB = dC0 = None
         if ctx.needs_input_grad[1]:
-            dA = torch.empty(A.shape, dtype=A.dtype, device=A.device)
+            dA = torch.empty_like(A, memory_format=torch.preserve_format)
             _contract(alpha, G, lc, B.detach(), lb, 0.0, dA, la, compute=compute)
         if ctx.needs_input_grad[3]:
-            dB = torch.empty(B.shape, dtype=B.dtype, device=B.device)
+            dB = torch.empty_like(B, memory_format=torch.preserve_format)
             _contract(alpha, A.detach(), la, G, lc, 0.0, dB, lb, compute=compute)
         if has_c0 and ctx.needs_input_grad[6]:
             dC0 = G * beta

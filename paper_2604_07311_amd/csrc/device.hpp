@@ -85,9 +85,7 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 // k; each thread owns KV consecutive k's (KV = 1 for the plain kernels, 2 for
 // the bf16 split, whose stores pack pairs) in E / KV rows.
 // Row-fast (otherwise): lanes run along the rows, each thread owns one row and
-// a run of E consecutive k's, stored to LDS as 16-byte vectors.  The k's are
-// the same for a whole wave when BR is a multiple of 64, so their offsets are
-// wave-uniform loads.
+// a run of E consecutive k's, stored to LDS as 16-byte vectors.
 // Rows past the problem edge carry offset 0 (a valid address) and only feed
 // accumulator rows that are never stored; k's past the edge are stored as 0.
 //
@@ -123,16 +121,33 @@ struct TileGather {
       for (int i = 0; i < E / KV; ++i) mn[i] = mnoff[tile_r0 + r0 + i * RSTEP];
     } else {
       r0 = tid % BR;
+      // The k run is the same for a whole wave, but its offsets are fetched
+      // with vector loads on purpose: scalar loads share the LDS wait
+      // counter, and every wait for an MFMA operand read would then also wait
+      // for the offsets of a slice two steps ahead.
       kk0 = (tid / BR) * E;
-      if constexpr (BR % 64 == 0) kk0 = __builtin_amdgcn_readfirstlane(kk0);
       mn[0] = mnoff[tile_r0 + r0];
     }
   }
 
-  // Offsets of slice [k0, k0 + BK); koff must hold k0 + BK entries.
+  // Offsets of slice [k0, k0 + BK); koff must hold k0 + BK entries.  Row-fast
+  // runs are read as 16-byte vectors: every indexing vector starts on a
+  // 64-byte boundary and k0 + kk0 is a multiple of E.
+  static constexpr int OV = 16 / (int)sizeof(OffT);
   __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
+    if constexpr (!KFAST && E % OV == 0) {
+      typedef OffT ovec_t __attribute__((ext_vector_type(16 / sizeof(OffT))));
+      const ovec_t* src = reinterpret_cast<const ovec_t*>(koff + k0 + kk0);
 #pragma unroll
-    for (int u = 0; u < (KFAST ? KV : E); ++u) ko[u] = koff[k0 + kk0 + u];
+      for (int q = 0; q < E / OV; ++q) {
+        const ovec_t w = src[q];
+#pragma unroll
+        for (int u = 0; u < OV; ++u) ko[q * OV + u] = w[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < (KFAST ? KV : E); ++u) ko[u] = koff[k0 + kk0 + u];
+    }
   }
 
   __device__ __forceinline__ void load(const T* __restrict__ base) {
@@ -148,24 +163,40 @@ struct TileGather {
     return k0 + krel(j) < kend ? v[j] : T(0);
   }
 
+  // value() where EDGE, the raw element otherwise (slices wholly inside K).
+  template <bool EDGE>
+  __device__ __forceinline__ T val(int j, int k0, int kend) const {
+    return EDGE ? value(j, k0, kend) : v[j];
+  }
+
   __device__ __forceinline__ int lds_index(int j, int ldk) const {
     return KFAST ? (r0 + (j / KV) * RSTEP) * ldk + kk0 + j % KV : r0 * ldk + kk0 + j;
   }
 
-  __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
+  // Store the slice to LDS, zeroing k's past kend.  Only the last slice of a
+  // K range can hold such k's, so the test is skipped (a uniform branch) on
+  // every other slice.
+  template <bool EDGE>
+  __device__ __forceinline__ void store_impl(T* __restrict__ lds, int k0, int kend) const {
     if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) lds[lds_index(j, LDK)] = value(j, k0, kend);
+      for (int j = 0; j < E; ++j) lds[lds_index(j, LDK)] = val<EDGE>(j, k0, kend);
     } else {
       typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
 #pragma unroll
       for (int q = 0; q < E / VK; ++q) {
         vec_t w;
 #pragma unroll
-        for (int u = 0; u < VK; ++u) w[u] = value(q * VK + u, k0, kend);
+        for (int u = 0; u < VK; ++u) w[u] = val<EDGE>(q * VK + u, k0, kend);
         *reinterpret_cast<vec_t*>(lds + r0 * LDK + kk0 + q * VK) = w;
       }
     }
+  }
+  __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
+    if (k0 + BK <= kend)
+      store_impl<false>(lds, k0, kend);
+    else
+      store_impl<true>(lds, k0, kend);
   }
 };
 

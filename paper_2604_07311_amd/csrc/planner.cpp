@@ -224,22 +224,20 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   drop1(P);
   drop1(Lm);
 
-  // Orientation: the kernel's N runs along the MFMA lane index, so C's
-  // smallest-stride mode should be a column mode.  If it is a row mode,
-  // compute C^T = B^T A^T: exchange the operands and the two groups.
-  int64_t ci = min_abs(I, 2), cj = min_abs(J, 2);
-  an.swapped = (!I.empty() && ci < cj);
-  if (an.swapped) {
-    std::swap(I, J);
-    std::swap(M, N);
-    for (Mode& m : I) std::swap(m.sx, m.sy);
-    for (Mode& m : J) std::swap(m.sx, m.sy);
-    for (Mode& m : P) std::swap(m.sx, m.sy);
-    for (Mode& m : Lm) std::swap(m.sx, m.sy);
-  }
-
-  // Order: rows and columns by C's stride; contracted modes by the operand
-  // with the smaller contracted stride (ties broken by the other operand).
+  // Orientation and mode order.  The kernel gathers its X operand along rows
+  // or along K, Y along columns or along K, taking per operand the direction
+  // whose first mode has the smaller stride, and writes C with lanes along
+  // its columns (the MFMA lane index).  A direction whose first mode has unit
+  // stride is coalesced; a stride of s elements spreads a wave's accesses
+  // over about s times as many cache lines (counted up to 16).  Per output
+  // element and 128 x 128 tile, X and Y each move K/128 elements and C two
+  // (read and write), so a choice costs
+  //     K/128 * (cost_X + cost_Y) + 2 * cost_C,
+  // minimised over the orientation (C = A B or C^T = B^T A^T) and, per group,
+  // the operand whose strides order it (rows: C or X, columns: C or Y,
+  // contracted: X or Y).  The default (C's smallest stride along the
+  // columns, rows and columns in C's order, contracted modes in the order of
+  // the operand with the smaller contracted stride) wins ties.
   auto by = [](int w1, int w2) {
     return [w1, w2](const Mode& a, const Mode& b) {
       int64_t x = iabs(sel(a, w1)), y = iabs(sel(b, w1));
@@ -247,15 +245,53 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
       return iabs(sel(a, w2)) < iabs(sel(b, w2));
     };
   };
-  std::stable_sort(I.begin(), I.end(), by(2, 0));
-  std::stable_sort(J.begin(), J.end(), by(2, 1));
-  if (min_abs(P, 0) <= min_abs(P, 1))
-    std::stable_sort(P.begin(), P.end(), by(0, 1));
-  else
-    std::stable_sort(P.begin(), P.end(), by(1, 0));
-  an.I = fuse(I, 0, 2);
-  an.J = fuse(J, 1, 2);
-  an.P = fuse(P, 0, 1);
+  auto first = [](const std::vector<Mode>& g, int which) {
+    return g.empty() ? std::numeric_limits<int64_t>::max() : iabs(sel(g.front(), which));
+  };
+  // cost of gathering one operand: the better of its two directions
+  auto gather_cost = [&](const std::vector<Mode>& free, const std::vector<Mode>& con, int which) {
+    const int64_t st = std::min(first(free, which), first(con, which));
+    return (double)std::min<int64_t>(std::max<int64_t>(st, 1), 16);
+  };
+  struct Choice {
+    bool swapped;
+    std::vector<Mode> I, J, P;
+    double cost;
+  };
+  auto evaluate = [&](bool swp, int io, int jo, int po) {
+    Choice ch{swp, I, J, P, 0.0};
+    if (swp) {
+      std::swap(ch.I, ch.J);
+      for (Mode& m : ch.I) std::swap(m.sx, m.sy);
+      for (Mode& m : ch.J) std::swap(m.sx, m.sy);
+      for (Mode& m : ch.P) std::swap(m.sx, m.sy);
+    }
+    std::stable_sort(ch.I.begin(), ch.I.end(), io == 0 ? by(2, 0) : by(0, 2));
+    std::stable_sort(ch.J.begin(), ch.J.end(), jo == 0 ? by(2, 1) : by(1, 2));
+    if (po < 0) po = min_abs(ch.P, 0) <= min_abs(ch.P, 1) ? 0 : 1;
+    std::stable_sort(ch.P.begin(), ch.P.end(), po == 0 ? by(0, 1) : by(1, 0));
+    const double cx = gather_cost(ch.I, ch.P, 0), cy = gather_cost(ch.J, ch.P, 1);
+    const double cc = ch.J.empty() ? 1.0 : gather_cost(ch.J, {}, 2);
+    ch.cost = (double)K / 128.0 * (cx + cy) + 2.0 * cc;
+    return ch;
+  };
+  const bool swap0 = !I.empty() && min_abs(I, 2) < min_abs(J, 2);
+  Choice best = evaluate(swap0, 0, 0, -1);
+  for (int swp = 0; swp < 2; ++swp)
+    for (int io = 0; io < 2; ++io)
+      for (int jo = 0; jo < 2; ++jo)
+        for (int po = 0; po < 2; ++po) {
+          Choice ch = evaluate(swp != 0, io, jo, po);
+          if (ch.cost < best.cost * (1.0 - 1e-9)) best = std::move(ch);
+        }
+  an.swapped = best.swapped;
+  if (an.swapped) {
+    std::swap(M, N);
+    for (Mode& m : Lm) std::swap(m.sx, m.sy);
+  }
+  an.I = fuse(best.I, 0, 2);
+  an.J = fuse(best.J, 1, 2);
+  an.P = fuse(best.P, 0, 1);
   std::stable_sort(Lm.begin(), Lm.end(), by(2, 0));
   an.Lm = Lm;  // batch modes: not fused (one offset per batch index in each operand)
   an.M = M;
@@ -263,10 +299,11 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   an.K = K;
   an.L = L;
 
-  // Gather direction per operand: along the contracted modes when one of them
-  // has the operand's smallest stride (ties go to K, the LDS-contiguous way).
-  an.x_kfast = an.P.empty() ? false : (an.I.empty() || min_abs(an.P, 0) <= min_abs(an.I, 0));
-  an.y_kfast = an.P.empty() ? false : (an.J.empty() || min_abs(an.P, 1) <= min_abs(an.J, 1));
+  // Gather direction per operand: along the contracted modes unless the free
+  // group's first mode has a strictly smaller stride (ties go to K, the
+  // LDS-contiguous way; an empty free group has no rows to gather along).
+  an.x_kfast = !an.P.empty() && first(an.P, 0) <= first(an.I, 0);
+  an.y_kfast = !an.P.empty() && first(an.P, 1) <= first(an.J, 1);
   an.max_abs_x = reach(an.I, 0) + reach(an.P, 0) + reach(an.Lm, 0);
   an.max_abs_y = reach(an.J, 1) + reach(an.P, 1) + reach(an.Lm, 1);
   an.max_abs_c = reach(an.I, 2) + reach(an.J, 2) + reach(an.Lm, 2);

@@ -46,15 +46,15 @@ constexpr int kB3LD = kB3K + 8;     // row pitch in bf16
 // Write the split of a gathered slice into the NS part tiles (part t at
 // tiles + t * tile_elems).  K-gathered threads own pairs of consecutive k's
 // (one packed dword per row and part); row-gathered threads own a run of k's
-// in one row (8-byte stores).
-template <int NS, typename G, bool KFAST>
+// in one row (8-byte stores).  EDGE: the slice reaches past kend.
+template <int NS, typename G, bool KFAST, bool EDGE>
 __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile_elems, int k0, int kend) {
   if constexpr (KFAST) {
     static_assert(G::KVT == 2, "K-gathered bf16 split stores pairs of k");
 #pragma unroll
     for (int i = 0; i < G::E / 2; ++i) {
       uint32_t p[NS];
-      split2<NS>(gg.value(2 * i, k0, kend), gg.value(2 * i + 1, k0, kend), p);
+      split2<NS>(gg.template val<EDGE>(2 * i, k0, kend), gg.template val<EDGE>(2 * i + 1, k0, kend), p);
       const int idx = gg.lds_index(2 * i, kB3LD);
 #pragma unroll
       for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
@@ -64,8 +64,8 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
 #pragma unroll
     for (int q = 0; q < G::E / 4; ++q) {
       uint32_t p0[NS], p1[NS];
-      split2<NS>(gg.value(4 * q, k0, kend), gg.value(4 * q + 1, k0, kend), p0);
-      split2<NS>(gg.value(4 * q + 2, k0, kend), gg.value(4 * q + 3, k0, kend), p1);
+      split2<NS>(gg.template val<EDGE>(4 * q, k0, kend), gg.template val<EDGE>(4 * q + 1, k0, kend), p0);
+      split2<NS>(gg.template val<EDGE>(4 * q + 2, k0, kend), gg.template val<EDGE>(4 * q + 3, k0, kend), p1);
       const int idx = gg.lds_index(4 * q, kB3LD);
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
@@ -90,7 +90,10 @@ struct SplitLoader {
   __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
   __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int k0, int kend) const {
-    store_split<NS, G, KF>(g, tiles, tile_elems, k0, kend);
+    if (k0 + kB3K <= kend)
+      store_split<NS, G, KF, false>(g, tiles, tile_elems, k0, kend);
+    else
+      store_split<NS, G, KF, true>(g, tiles, tile_elems, k0, kend);
   }
 };
 
