@@ -168,6 +168,31 @@ def test_general_label_classification(fm):
     assert sorted((info["m"], info["n"])) == [3, 6] and info["k"] == 10   # k = 5 (k) * 2 (t)
 
 
+def test_cost_model_orders_rows_by_the_gathered_operand(fm, oracle_lib):
+    """C[j,i1,i2] is unit-stride along j, so the rows i1, i2 would follow C's
+    order (i1 first); A stores i2 fastest.  Ordering the rows by C would make
+    every row gather of A stride e2 elements; the planner orders them by A
+    instead (C's column writes do not depend on the row order)."""
+    e = {"i": 20, "k": 24, "j": 30, "p": 40}
+    a = synth.layout([e["i"], e["k"], e["p"]], order=[1, 0, 2])      # A[i,k,p]: k fastest
+    b = synth.layout([e["p"], e["j"]])                                 # B[p,j]: p fastest
+    c = synth.layout([e["j"], e["i"], e["k"]])                         # C[j,i,k]: j fastest
+    p = synth.Problem("rows_by_x", "ikp", "pj", "jik", a, b, c, 1.0, 0.0)
+    info, off = analyze(fm, p, offsets=True)
+    assert info["swapped"] == 0 and info["x_kfast"] == 0 and info["y_kfast"] == 1
+    steps = np.diff(off["xrow"][: e["k"]])
+    assert np.all(steps == 1)                      # coalesced row gather of A
+    assert np.all(np.diff(off["yk"][: e["p"]]) == 1)
+    assert np.all(np.diff(off["ccol"][: e["j"]]) == 1)
+    # the reordered rows still address C consistently: kernel view == oracle
+    import oracle
+    rng = np.random.default_rng(7)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    _, out = _kernel_view_numpy(fm, p)
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    np.testing.assert_array_equal(out, want)
+
+
 def test_negative_and_zero_strides_offsets(fm):
     a = synth.layout([3, 4], negate=[True, False])
     b = synth.layout([4, 5], zero=[False, True])
