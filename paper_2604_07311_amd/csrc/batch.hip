@@ -6,7 +6,8 @@
 // into (problem, tile) work items and deals them to a fixed grid of
 // workgroups: problems are spread over the XCDs by estimated cost (so a
 // problem's tiles share one L2), and inside an XCD items go, largest first,
-// to the least-loaded workgroup (longest-processing-time-first).  The device
+// to the least-loaded workgroup (longest-processing-time-first), so a
+// problem's tiles run side by side on different workgroups.  The device
 // work list is static, so a launch needs no counters, no atomics and no
 // clearing, and can be captured in a HIP graph and replayed.  This is the
 // on-GPU counterpart of running many tile-sized contractions (Approach,
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void batch_scale(BatchArgs a, const int32
   const T be = static_cast<T>(a.beta);
   for (int64_t i = threadIdx.x; i < mn; i += kThreads) {
     const int m = (int)(i / P.N), nn = (int)(i % P.N);
-    T* cp = at(C, (uint32_t)(o[P.pos[4] + m] + o[P.pos[5] + nn]));
+    auto* cp = global(at(C, (uint32_t)(o[P.pos[4] + m] + o[P.pos[5] + nn])));
     *cp = be != T(0) ? be * *cp : T(0);
   }
 }
@@ -276,11 +277,17 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     for (const Job& jb : per_prob[(size_t)p]) xjobs[(size_t)x].push_back(jb);
   }
   // 2) inside an XCD: items, largest first, to its least-loaded workgroup
-  //    (workgroup w runs on XCD w % 8)
+  //    (workgroup w runs on XCD w % 8).  A problem's tiles are consecutive in
+  //    this order, so they go to different workgroups at about the same
+  //    estimated time and run side by side: their shared operand panels are
+  //    then read once into the XCD's L2 instead of once per tile.  Each
+  //    workgroup keeps its items in start-time order for the same reason.
   std::vector<std::vector<Job>> wjobs((size_t)grid);
   for (int x = 0; x < 8; ++x) {
     auto& js = xjobs[(size_t)x];
-    std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) { return a.cost > b.cost; });
+    std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) {
+      return a.cost != b.cost ? a.cost > b.cost : a.prob < b.prob;
+    });
     typedef std::pair<double, int> Slot;
     std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
     for (int k = 0; k < per_xcd; ++k) heap.push({0.0, x + 8 * k});
@@ -295,10 +302,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   std::vector<int32_t> wg_start((size_t)grid + 1, 0);
   for (int w = 0; w < grid; ++w) {
     wg_start[(size_t)w] = (int32_t)items.size();
-    auto& js = wjobs[(size_t)w];
-    // within a workgroup, run a problem's tiles back to back (operand reuse)
-    std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) { return a.prob < b.prob; });
-    for (const Job& jb : js) items.push_back({jb.prob, jb.tm, jb.tn});
+    for (const Job& jb : wjobs[(size_t)w]) items.push_back({jb.prob, jb.tm, jb.tn});
   }
   wg_start[(size_t)grid] = (int32_t)items.size();
   bp->grid = grid;
@@ -318,14 +322,22 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     return hip_fail(e, "hipMalloc(batched plan)");
   }
   char* base = static_cast<char*>(bp->d_buf);
-  std::vector<char> host(total, 0);
-  std::memcpy(host.data(), probs.data(), probs.size() * sizeof(BatchProblemDev));
-  std::memcpy(host.data() + s_probs, items.data(), items.size() * sizeof(BatchItem));
-  std::memcpy(host.data() + s_probs + s_items, wg_start.data(), wg_start.size() * sizeof(int32_t));
-  std::memcpy(host.data() + s_probs + s_items + s_wg, bp->scale_only.data(),
-              bp->scale_only.size() * sizeof(int32_t));
-  std::memcpy(host.data() + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(uint32_t));
-  e = hipMemcpy(bp->d_buf, host.data(), total, hipMemcpyHostToDevice);
+  // Staged through pinned host memory: a pageable copy of this size would go
+  // through the runtime's staging buffer in many small pieces.
+  char* host = nullptr;
+  e = hipHostMalloc(reinterpret_cast<void**>(&host), total, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete bp;
+    return hip_fail(e, "hipHostMalloc(batched plan staging)");
+  }
+  std::memset(host, 0, total);
+  std::memcpy(host, probs.data(), probs.size() * sizeof(BatchProblemDev));
+  std::memcpy(host + s_probs, items.data(), items.size() * sizeof(BatchItem));
+  std::memcpy(host + s_probs + s_items, wg_start.data(), wg_start.size() * sizeof(int32_t));
+  std::memcpy(host + s_probs + s_items + s_wg, bp->scale_only.data(), bp->scale_only.size() * sizeof(int32_t));
+  std::memcpy(host + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(uint32_t));
+  e = hipMemcpy(bp->d_buf, host, total, hipMemcpyHostToDevice);
+  (void)hipHostFree(host);
   if (e != hipSuccess) {
     delete bp;
     return hip_fail(e, "hipMemcpy(batched plan)");

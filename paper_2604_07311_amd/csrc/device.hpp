@@ -45,6 +45,23 @@ __device__ __forceinline__ T* at(T* base, int64_t off) {
   return base + off;
 }
 
+// Operands always live in global memory.  Loads and stores through these
+// helpers say so, so they compile to global (not flat) instructions even when
+// the pointer was read from memory, as in the batched kernel: a flat load
+// takes a 64-bit VGPR address and is counted by the LDS wait counter too.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+template <typename T, typename OffT>
+__device__ __forceinline__ T gload(const T* base, OffT off) {
+  return *global(at(base, off));
+}
+
 // MFMA shapes.  In every shape the lane index l selects the row (of the left
 // operand) and the column (of the right operand) as l % BS, and the group
 // l / BS selects the contraction index, the same way for both operands, so
@@ -94,7 +111,9 @@ struct Mfma<float> {  // v_mfma_f32_32x32x2_f32
 // the next slice (nothing waits on them until store()), store() writes the
 // slice into LDS, zeroing k >= kend.  Element j of a thread is
 // (row j / KV, k j % KV) in the KFAST case and (row 0, k j) otherwise.
-template <typename T, typename OffT, int BR, int BK, bool KFAST, int KV = 1>
+// NSLOT > 1 keeps that many slices in flight: each phase takes the slot it
+// works on as a template argument.
+template <typename T, typename OffT, int BR, int BK, bool KFAST, int KV = 1, int NSLOT = 1>
 struct TileGather {
   static constexpr int E = BR * BK / kThreads;
   static constexpr int KVT = KV;                  // KFAST: consecutive k's per thread
@@ -109,8 +128,8 @@ struct TileGather {
                 "tile shape does not divide the workgroup");
 
   OffT mn[KFAST ? E / KV : 1];  // row offsets, fixed for the tile
-  OffT ko[KFAST ? KV : E];      // contracted-index offsets of the slice to load next
-  T v[E];
+  OffT ko[NSLOT][KFAST ? KV : E];  // contracted-index offsets of a slice to load
+  T v[NSLOT][E];
   int r0, kk0;  // first row; first k of the thread's run
 
   __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
@@ -134,6 +153,7 @@ struct TileGather {
   // runs are read as 16-byte vectors: every indexing vector starts on a
   // 64-byte boundary and k0 + kk0 is a multiple of E.
   static constexpr int OV = 16 / (int)sizeof(OffT);
+  template <int S = 0>
   __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
     if constexpr (!KFAST && E % OV == 0) {
       typedef OffT ovec_t __attribute__((ext_vector_type(16 / sizeof(OffT))));
@@ -142,31 +162,33 @@ struct TileGather {
       for (int q = 0; q < E / OV; ++q) {
         const ovec_t w = src[q];
 #pragma unroll
-        for (int u = 0; u < OV; ++u) ko[q * OV + u] = w[u];
+        for (int u = 0; u < OV; ++u) ko[S][q * OV + u] = w[u];
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < (KFAST ? KV : E); ++u) ko[u] = koff[k0 + kk0 + u];
+      for (int u = 0; u < (KFAST ? KV : E); ++u) ko[S][u] = koff[k0 + kk0 + u];
     }
   }
 
+  template <int S = 0>
   __device__ __forceinline__ void load(const T* __restrict__ base) {
 #pragma unroll
     for (int j = 0; j < E; ++j)
-      v[j] = KFAST ? *at(base, (OffT)(mn[j / KV] + ko[j % KV])) : *at(base, (OffT)(mn[0] + ko[j]));
+      v[S][j] = KFAST ? gload(base, (OffT)(mn[j / KV] + ko[S][j % KV])) : gload(base, (OffT)(mn[0] + ko[S][j]));
   }
 
   __device__ __forceinline__ int krel(int j) const { return kk0 + (KFAST ? j % KV : j); }
 
   // Value of element j of the slice starting at k0 (0 past kend).
+  template <int S = 0>
   __device__ __forceinline__ T value(int j, int k0, int kend) const {
-    return k0 + krel(j) < kend ? v[j] : T(0);
+    return k0 + krel(j) < kend ? v[S][j] : T(0);
   }
 
   // value() where EDGE, the raw element otherwise (slices wholly inside K).
-  template <bool EDGE>
+  template <bool EDGE, int S = 0>
   __device__ __forceinline__ T val(int j, int k0, int kend) const {
-    return EDGE ? value(j, k0, kend) : v[j];
+    return EDGE ? value<S>(j, k0, kend) : v[S][j];
   }
 
   __device__ __forceinline__ int lds_index(int j, int ldk) const {
@@ -176,27 +198,28 @@ struct TileGather {
   // Store the slice to LDS, zeroing k's past kend.  Only the last slice of a
   // K range can hold such k's, so the test is skipped (a uniform branch) on
   // every other slice.
-  template <bool EDGE>
+  template <bool EDGE, int S>
   __device__ __forceinline__ void store_impl(T* __restrict__ lds, int k0, int kend) const {
     if constexpr (KFAST) {
 #pragma unroll
-      for (int j = 0; j < E; ++j) lds[lds_index(j, LDK)] = val<EDGE>(j, k0, kend);
+      for (int j = 0; j < E; ++j) lds[lds_index(j, LDK)] = val<EDGE, S>(j, k0, kend);
     } else {
       typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
 #pragma unroll
       for (int q = 0; q < E / VK; ++q) {
         vec_t w;
 #pragma unroll
-        for (int u = 0; u < VK; ++u) w[u] = val<EDGE>(q * VK + u, k0, kend);
+        for (int u = 0; u < VK; ++u) w[u] = val<EDGE, S>(q * VK + u, k0, kend);
         *reinterpret_cast<vec_t*>(lds + r0 * LDK + kk0 + q * VK) = w;
       }
     }
   }
+  template <int S = 0>
   __device__ __forceinline__ void store(T* __restrict__ lds, int k0, int kend) const {
     if (k0 + BK <= kend)
-      store_impl<false>(lds, k0, kend);
+      store_impl<false, S>(lds, k0, kend);
     else
-      store_impl<true>(lds, k0, kend);
+      store_impl<true, S>(lds, k0, kend);
   }
 };
 
@@ -206,7 +229,7 @@ struct TileGather {
 // (tile, kb) is BR x BK elements stored [row][k] densely, zero-filled past the
 // problem edges, blocks ordered tile-major (tile * nkb + kb).  A slice is then
 // a contiguous run of 16-byte vectors: no indexing vectors, no edge tests.
-template <typename T, int BR, int BK>
+template <typename T, int BR, int BK, int NSLOT = 1>
 struct PackedGather {
   static constexpr int VK = 16 / (int)sizeof(T);
   static constexpr int LDK = BK + VK;
@@ -214,36 +237,38 @@ struct PackedGather {
   static constexpr int VPT = NV / kThreads;
   static_assert(NV % kThreads == 0 && BK % VK == 0, "packed block does not divide the workgroup");
   typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
-  vec_t v[VPT];
-  int tile = 0, kb = 0, nkb = 1, tid = 0;
+  vec_t v[NSLOT][VPT];
+  int tile = 0, kb[NSLOT] = {}, nkb = 1, tid = 0;
 
   template <typename OffT>
   __device__ __forceinline__ void init(const OffT* /*unused*/, int tile_r0, int t) {
     tile = tile_r0 / BR;
     tid = t;
   }
-  template <typename OffT>
+  template <int S = 0, typename OffT>
   __device__ __forceinline__ void fetch_k(const OffT* /*unused*/, int k0) {
-    kb = k0 / BK;
+    kb[S] = k0 / BK;
   }
+  template <int S = 0>
   __device__ __forceinline__ void load(const T* __restrict__ base) {
-    const vec_t* blk = reinterpret_cast<const vec_t*>(base + ((size_t)tile * nkb + kb) * (size_t)(BR * BK));
+    const vec_t* blk = reinterpret_cast<const vec_t*>(base + ((size_t)tile * nkb + kb[S]) * (size_t)(BR * BK));
 #pragma unroll
-    for (int q = 0; q < VPT; ++q) v[q] = blk[tid + q * kThreads];
+    for (int q = 0; q < VPT; ++q) v[S][q] = *global(blk + tid + q * kThreads);
   }
+  template <int S = 0>
   __device__ __forceinline__ void store(T* __restrict__ lds, int /*k0*/, int /*kend*/) const {
 #pragma unroll
     for (int q = 0; q < VPT; ++q) {
       const int e = (tid + q * kThreads) * VK;
-      *reinterpret_cast<vec_t*>(lds + (e / BK) * LDK + e % BK) = v[q];
+      *reinterpret_cast<vec_t*>(lds + (e / BK) * LDK + e % BK) = v[S][q];
     }
   }
 };
 
 // Operand loaders by mode: 0 row-gathered, 1 K-gathered, 2 pre-packed.
 enum { kRowGather = 0, kKGather = 1, kPacked = 2 };
-template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1>
-using Loader = typename std::conditional<MODE == kPacked, PackedGather<T, BR, BK>,
-                                         TileGather<T, OffT, BR, BK, MODE == kKGather, KV>>::type;
+template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1, int NSLOT = 1>
+using Loader = typename std::conditional<MODE == kPacked, PackedGather<T, BR, BK, NSLOT>,
+                                         TileGather<T, OffT, BR, BK, MODE == kKGather, KV, NSLOT>>::type;
 
 }  // namespace famlies

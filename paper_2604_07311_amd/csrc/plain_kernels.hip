@@ -22,7 +22,15 @@ namespace famlies {
 
 template <typename T, typename OffT, int BM, int BN, int BK, int XM, int YM>
 __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_contract(PlainArgs<OffT> a) {
-  using Tile = PlainTile<T, BM, BN, BK, XM, YM>;
+  // A row-gathered operand issues one load per element along K, so its slice
+  // takes longer to arrive: FP32 tiles with 32-bit offsets then keep two
+  // slices in flight (measured: ring FP32, Y row-gathered, 69.8 % -> 75.7 %
+  // of peak; with both operands K-gathered the deeper pipeline lost 8 %).
+  // FP64 tiles need every register for the accumulators, and 64-bit offsets
+  // double the registers of the indexing vectors.
+  static constexpr int kDepth =
+      (sizeof(T) == 4 && sizeof(OffT) == 4 && (XM == kRowGather || YM == kRowGather)) ? 2 : 1;
+  using Tile = PlainTile<T, BM, BN, BK, XM, YM, kDepth>;
   __shared__ T smem[Tile::SMEM];
   const int lid0 = xcd_remap(blockIdx.x, gridDim.x);
   const int ntiles = a.tiles_m * a.tiles_n;

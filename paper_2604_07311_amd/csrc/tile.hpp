@@ -6,6 +6,8 @@
 //   -> alpha/beta scatter-update of C, or FP partial sums for split-K
 #pragma once
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace famlies {
@@ -29,14 +31,17 @@ struct TileJob {
   int x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y
 };
 
-// XM, YM: operand loader modes (kRowGather, kKGather, kPacked).
-template <typename T, int BM, int BN, int BK, int XM, int YM>
+// XM, YM: operand loader modes (kRowGather, kKGather, kPacked).  DEPTH: K
+// slices whose data loads are in flight while a slice is multiplied (1: the
+// next slice; 2: the next two, for latency-bound gathers when registers
+// allow).
+template <typename T, int BM, int BN, int BK, int XM, int YM, int DEPTH = 1>
 struct PlainTile {
   using MF = Mfma<T>;
   template <typename OffT>
-  using GX = Loader<T, OffT, BM, BK, XM>;
+  using GX = Loader<T, OffT, BM, BK, XM, 1, DEPTH>;
   template <typename OffT>
-  using GY = Loader<T, OffT, BN, BK, YM>;
+  using GY = Loader<T, OffT, BN, BK, YM, 1, DEPTH>;
   static constexpr int LX = GX<int32_t>::LDK;
   static constexpr int LY = GY<int32_t>::LDK;
   static constexpr int XS = BM * LX, YS = BN * LY;
@@ -45,6 +50,25 @@ struct PlainTile {
   static constexpr int MB = WTM / MF::BS, NB = WTN / MF::BS;
   static constexpr int KPG = BK / MF::KG;
   static_assert(MB >= 1 && NB >= 1 && BK % MF::KG == 0, "bad tile");
+  static_assert(DEPTH == 1 || DEPTH == 2, "pipeline depth 1 or 2");
+
+  // One slice from LDS buffer `xs` into the accumulators.
+  __device__ __forceinline__ static void multiply(const T* xs, int wm, int wn, int g, int r,
+                                                  typename MF::Acc (&acc)[MB][NB]) {
+    const T* ys = xs + XS;
+#pragma unroll
+    for (int s = 0; s < KPG; ++s) {
+      T av[MB], bv[NB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) av[i] = xs[(wm * WTM + i * MF::BS + r) * LX + g * KPG + s];
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) bv[jj] = ys[(wn * WTN + jj * MF::BS + r) * LY + g * KPG + s];
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) acc[i][jj] = MF::mma(av[i], bv[jj], acc[i][jj]);
+    }
+  }
 
   template <typename OffT>
   __device__ __forceinline__ static void run(const TileJob<OffT>& j, T* smem) {
@@ -69,51 +93,85 @@ struct PlainTile {
       for (int jj = 0; jj < NB; ++jj) acc[i][jj] = typename MF::Acc{};
 
     const int g = lane / MF::BS, r = lane % MF::BS;
-    if (nk > 0) {
-      // pipeline: offsets two slices ahead, data one slice ahead, LDS double buffer
-      gx.fetch_k(j.xk, j.kbeg);
-      gy.fetch_k(j.yk, j.kbeg);
-      gx.load(X);
-      gy.load(Y);
-      if (nk > 1) {
-        gx.fetch_k(j.xk, j.kbeg + BK);
-        gy.fetch_k(j.yk, j.kbeg + BK);
-      }
-      gx.store(smem, j.kbeg, j.kend);
-      gy.store(smem + XS, j.kbeg, j.kend);
-      __syncthreads();
-      for (int it = 0; it < nk; ++it) {
-        const int cur = it & 1;
-        const bool more = it + 1 < nk;
-        if (more) {
-          gx.load(X);
-          gy.load(Y);
-          if (it + 2 < nk) {
-            gx.fetch_k(j.xk, j.kbeg + (it + 2) * BK);
-            gy.fetch_k(j.yk, j.kbeg + (it + 2) * BK);
+    if constexpr (DEPTH == 1) {
+      if (nk > 0) {
+        // pipeline: offsets two slices ahead, data one slice ahead, LDS double buffer
+        gx.fetch_k(j.xk, j.kbeg);
+        gy.fetch_k(j.yk, j.kbeg);
+        gx.load(X);
+        gy.load(Y);
+        if (nk > 1) {
+          gx.fetch_k(j.xk, j.kbeg + BK);
+          gy.fetch_k(j.yk, j.kbeg + BK);
+        }
+        gx.store(smem, j.kbeg, j.kend);
+        gy.store(smem + XS, j.kbeg, j.kend);
+        __syncthreads();
+        for (int it = 0; it < nk; ++it) {
+          const int cur = it & 1;
+          const bool more = it + 1 < nk;
+          if (more) {
+            gx.load(X);
+            gy.load(Y);
+            if (it + 2 < nk) {
+              gx.fetch_k(j.xk, j.kbeg + (it + 2) * BK);
+              gy.fetch_k(j.yk, j.kbeg + (it + 2) * BK);
+            }
           }
+          multiply(smem + cur * (XS + YS), wm, wn, g, r, acc);
+          if (more) {
+            T* nx = smem + (cur ^ 1) * (XS + YS);
+            const int kn = j.kbeg + (it + 1) * BK;
+            gx.store(nx, kn, j.kend);
+            gy.store(nx + XS, kn, j.kend);
+          }
+          __syncthreads();
         }
-        const T* xs = smem + cur * (XS + YS);
-        const T* ys = xs + XS;
-#pragma unroll
-        for (int s = 0; s < KPG; ++s) {
-          T av[MB], bv[NB];
-#pragma unroll
-          for (int i = 0; i < MB; ++i) av[i] = xs[(wm * WTM + i * MF::BS + r) * LX + g * KPG + s];
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) bv[jj] = ys[(wn * WTN + jj * MF::BS + r) * LY + g * KPG + s];
-#pragma unroll
-          for (int i = 0; i < MB; ++i)
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj) acc[i][jj] = MF::mma(av[i], bv[jj], acc[i][jj]);
+      }
+    } else if (nk > 0) {
+      // DEPTH 2: slice s lives in register slot s % 2 and LDS buffer s % 2;
+      // data two slices ahead, offsets three ahead.
+      gx.template fetch_k<0>(j.xk, j.kbeg);
+      gy.template fetch_k<0>(j.yk, j.kbeg);
+      gx.template load<0>(X);
+      gy.template load<0>(Y);
+      if (nk > 1) {
+        gx.template fetch_k<1>(j.xk, j.kbeg + BK);
+        gy.template fetch_k<1>(j.yk, j.kbeg + BK);
+        gx.template load<1>(X);
+        gy.template load<1>(Y);
+      }
+      if (nk > 2) {
+        gx.template fetch_k<0>(j.xk, j.kbeg + 2 * BK);
+        gy.template fetch_k<0>(j.yk, j.kbeg + 2 * BK);
+      }
+      gx.template store<0>(smem, j.kbeg, j.kend);
+      gy.template store<0>(smem + XS, j.kbeg, j.kend);
+      __syncthreads();
+      // Step for slice `it` held in LDS buffer S (it % 2 == S): slot S is free
+      // and holds the offsets of slice it + 2; slot S^1 holds slice it + 1.
+      auto step = [&](auto sc, int it) {
+        constexpr int S = decltype(sc)::value;
+        if (it + 2 < nk) {
+          gx.template load<S>(X);
+          gy.template load<S>(Y);
         }
-        if (more) {
-          T* nx = smem + (cur ^ 1) * (XS + YS);
+        if (it + 3 < nk) {
+          gx.template fetch_k<S ^ 1>(j.xk, j.kbeg + (it + 3) * BK);
+          gy.template fetch_k<S ^ 1>(j.yk, j.kbeg + (it + 3) * BK);
+        }
+        multiply(smem + S * (XS + YS), wm, wn, g, r, acc);
+        if (it + 1 < nk) {
+          T* nx = smem + (S ^ 1) * (XS + YS);
           const int kn = j.kbeg + (it + 1) * BK;
-          gx.store(nx, kn, j.kend);
-          gy.store(nx + XS, kn, j.kend);
+          gx.template store<S ^ 1>(nx, kn, j.kend);
+          gy.template store<S ^ 1>(nx + XS, kn, j.kend);
         }
         __syncthreads();
+      };
+      for (int it = 0; it < nk; it += 2) {
+        step(std::integral_constant<int, 0>{}, it);
+        if (it + 1 < nk) step(std::integral_constant<int, 1>{}, it + 1);
       }
     }
 
@@ -130,7 +188,7 @@ struct PlainTile {
           for (int e = 0; e < MF::NACC; ++e) {
             const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
             if (m < j.M && n < j.N) {
-              T* cp = at(C, (OffT)(j.cm[m] + cn));
+              auto* cp = global(at(C, (OffT)(j.cm[m] + cn)));
               T v = al * acc[i][jj][e];
               if (be != T(0)) v += be * *cp;
               *cp = v;
@@ -148,7 +206,7 @@ struct PlainTile {
 #pragma unroll
           for (int e = 0; e < MF::NACC; ++e) {
             const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
-            W[(size_t)m * j.ldw + n] = acc[i][jj][e];
+            *global(W + (size_t)m * j.ldw + n) = acc[i][jj][e];
           }
       }
     }
