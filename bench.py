@@ -144,6 +144,51 @@ class Single:
         del bufs
         return pack_ms, ms, launch, got
 
+    def torch_permute_matmul(self, steps, warmup):
+        """Context only: the route the method avoids.  The operands are
+        permuted into GEMM order and copied (permute().contiguous()), multiplied
+        with torch.matmul, and the product is scattered back into C's layout
+        with beta*C added.  Returns (ms for the whole route, ms for the matmul
+        alone, normwise difference from this library's C)."""
+        torch, p = self.torch, self.p
+        la, lb, lc = p.la, p.lb, p.lc
+        I = [ch for ch in lc if ch in la]
+        J = [ch for ch in lc if ch in lb]
+        P = [ch for ch in la if ch in lb]
+        ext = dict(zip(la + lb, list(p.a.extents) + list(p.b.extents)))
+        M = int(np.prod([ext[ch] for ch in I])) if I else 1
+        N = int(np.prod([ext[ch] for ch in J])) if J else 1
+        K = int(np.prod([ext[ch] for ch in P])) if P else 1
+        A = self.a.as_strided(p.a.extents, p.a.strides, p.a.base)
+        B = self.b.as_strided(p.b.extents, p.b.strides, p.b.base)
+        Cv = self.c.as_strided(p.c.extents, p.c.strides, p.c.base)
+        pa = [la.index(ch) for ch in I + P]
+        pb = [lb.index(ch) for ch in P + J]
+        # product laid out (I..., J...) -> permutation into C's label order
+        pc = [(I + J).index(ch) for ch in lc]
+        alpha, beta = p.alpha, p.beta
+
+        def route():
+            Xm = A.permute(pa).contiguous().reshape(M, K)
+            Ym = B.permute(pb).contiguous().reshape(K, N)
+            prod = torch.matmul(Xm, Ym).reshape([ext[ch] for ch in I + J]).permute(pc)
+            Cv.copy_(alpha * prod + beta * Cv)
+
+        Xm = A.permute(pa).contiguous().reshape(M, K)
+        Ym = B.permute(pb).contiguous().reshape(K, N)
+        ms_gemm, _, _ = Timer(self.stream).run(lambda: torch.matmul(Xm, Ym), steps, warmup)
+        del Xm, Ym
+        mine = self.result_once()
+        self.c.copy_(self.c0)
+        route()
+        torch.cuda.synchronize()
+        theirs = self.c.cpu().numpy().astype(np.float64)
+        diff = float(np.linalg.norm(theirs - mine) / max(np.linalg.norm(mine), 1e-300))
+        ms_route, _, _ = Timer(self.stream).run(route, steps, warmup)
+        self.c.copy_(self.c0)
+        torch.cuda.empty_cache()
+        return ms_route, ms_gemm, diff
+
     def result_once(self):
         """C after one call from C0 (float64 numpy storage)."""
         self.c.copy_(self.c0)
@@ -273,6 +318,14 @@ def wl_ladder(args):
         ms, launch, lmin = Timer(s.stream).run(s.step, args.steps, args.warmup)
         res[dtype] = {"ms": ms, "launch": launch, "info": s.info, "check": check, "plan_s": s.plan_s}
         log("%s: %.3f ms/step (%.1f GFLOP/s) check %s" % (dtype, ms, s.info["flops"] / ms / 1e6, check))
+        if args.context:
+            rms, gms, diff = s.torch_permute_matmul(max(3, args.steps // 2), 1)
+            res[dtype]["context_torch"] = {
+                "permute_copy_matmul_scatter_ms": round(rms, 4), "matmul_only_ms": round(gms, 4),
+                "gflops_route": round(s.info["flops"] / (rms * 1e-3) / 1e9, 2),
+                "gflops_matmul_only": round(s.info["flops"] / (gms * 1e-3) / 1e9, 2),
+                "normwise_diff_vs_this_library": diff}
+            log("%s torch permute+matmul: %.3f ms (matmul alone %.3f ms)" % (dtype, rms, gms))
         if args.pack:
             # W (operand A) pre-packed once, as a CC code reusing it across iterations would
             pack_ms, pms, plaunch, got = s.packed(1, args.steps, args.warmup)
@@ -296,6 +349,8 @@ def wl_ladder(args):
     out["roofline"] = roofline(flops, r["launch"], PEAK[head], key=("ladder", head, args.v, args.o))
     if "packed_W" in r:
         out["packed_W"] = r["packed_W"]
+    if "context_torch" in r:
+        out["context_torch"] = r["context_torch"]
     for dt, rr in res.items():
         if dt == head:
             continue
@@ -306,6 +361,8 @@ def wl_ladder(args):
             "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt], key=("ladder", dt, args.v, args.o))}
         if "packed_W" in rr:
             out["secondary"][dt]["packed_W"] = rr["packed_W"]
+        if "context_torch" in rr:
+            out["secondary"][dt]["context_torch"] = rr["context_torch"]
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(probs[head])
@@ -320,7 +377,9 @@ def _fp32_vs_bf16x3(args, p, name):
         ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
         res[comp] = {"ms": ms, "launch": launch, "info": s.info, "check": check}
         log("%s %s: %.3f ms (%.1f GFLOP/s) check %s" % (name, comp, ms, s.info["flops"] / ms / 1e6, check))
-        if args.pack and comp == "bf16x3":
+        if args.pack and comp == "bf16x3" and s.info["index_bits"] == 64:
+            res[comp]["packed"] = {"skipped": "operands span more than 4 GiB: 64-bit offsets, no packed kernel"}
+        elif args.pack and comp == "bf16x3":
             pack_ms, pms, plaunch, got = s.packed(3, args.steps, args.warmup)
             res[comp]["packed"] = {"pack_ms_once": round(pack_ms, 3), "ms_per_step": round(pms, 4),
                                    "gflops_fp32_equivalent": round(s.info["flops"] / (pms * 1e-3) / 1e9, 2),
@@ -401,8 +460,51 @@ def wl_plain16(args):
     out["error_vs_fp64"] = check
     out["roofline"] = roofline(flops, launch, PEAK["f64"])
     del g
+    out["batched_4096_instances"] = _plain16_batched(s, 4096, args)
     s.close()
     return out
+
+
+def _plain16_batched(s, n, args):
+    """The same 16^4 problem, n independent instances (read-only operands
+    shared, outputs disjoint) in one persistent batched launch from a graph:
+    what the shape reaches when the GPU is full."""
+    import torch
+    fm, p = s.fm, s.p
+    desc = lambda lay, lab: fm.make_desc(lay.extents, lay.strides, lab)
+    plan = fm.famlies_batch_plan(fm.handle(0), fm.FAMLIES_F64, [desc(p.a, p.la)] * n,
+                                 [desc(p.b, p.lb)] * n, [desc(p.c, p.lc)] * n)
+    C = s.c0.repeat(n)
+    csz = s.c0.numel()
+    pa = torch.full((n,), s.ptrs[0], dtype=torch.int64, device="cuda")
+    pb = torch.full((n,), s.ptrs[1], dtype=torch.int64, device="cuda")
+    pc = torch.tensor([C.data_ptr() + 8 * (i * csz + p.c.base) for i in range(n)], dtype=torch.int64,
+                      device="cuda")
+    stream = torch.cuda.Stream()
+
+    def launch():
+        fm.famlies_batch_execute(plan, p.alpha, p.beta, pa.data_ptr(), pb.data_ptr(), pc.data_ptr(),
+                                 stream.cuda_stream)
+
+    with torch.cuda.stream(stream):
+        launch()
+    torch.cuda.synchronize()
+    one = s.result_once()
+    got = C.reshape(n, csz)[[0, n // 2, n - 1]].cpu().numpy()
+    # the batched tiles sum K in another order than the split-K single call
+    diff = max(float(np.linalg.norm(g - one) / np.linalg.norm(one)) for g in got)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g, stream=stream):
+            launch()
+    torch.cuda.synchronize()
+    ms, _, _ = Timer(torch.cuda.current_stream()).run(g.replay, max(args.steps, 5), args.warmup)
+    flops = n * s.info["flops"]
+    fm.famlies_plan_destroy(plan)
+    del g
+    return {"instances": n, "ms": round(ms, 4), "gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+            "pct_fp64_peak": round(100 * flops / (ms * 1e-3) / PEAK["f64"], 2),
+            "normwise_diff_vs_single_call": diff}
 
 
 def wl_autograd(args):
@@ -527,6 +629,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pack", action="store_true",
                     help="also time the pre-packed path (ladder: W packed once; ring: both operands)")
+    ap.add_argument("--context", action="store_true",
+                    help="ladder: also time torch's permute().contiguous() + matmul route (context only)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device copy of this many bytes (a known-size "
                          "reference kernel for the HBM byte counters)")

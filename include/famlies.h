@@ -111,7 +111,8 @@ typedef struct {
   int32_t tile_m, tile_n, tile_k;
   int32_t split_k;          /* number of K slices (1 = none) */
   int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
-  int32_t kernel;           /* internal kernel variant id */
+  int32_t kernel;           /* 1 plain, 3 bf16x3, 4 bf16x6 (1 + bf16 parts per operand); +16 / +32 when the kernel reads X / Y
+                               from affine unit-stride K blocks with 16-byte loads (block strides) */
   double flops;             /* 2*batch*m*n*k */
 } famlies_plan_info;
 

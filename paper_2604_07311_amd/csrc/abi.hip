@@ -158,6 +158,46 @@ static int index_bits_for(const Analysis& an) {
 // the three int64 batch-offset vectors.  In the uint32 form every row vector
 // is rebased by its operand's lowest offset and all six are scaled to bytes;
 // sums row + col then land in [0, span) (unsigned wrap-around is exact).
+// Block strides of the block-scatter layout (Approach, "Supporting tensor
+// computations"): an operand gathered along K can be read with 16-byte loads
+// when, in every BK-block of K, its indexing vector steps by exactly one
+// element, and every run start (row offset + block start + batch offset, in
+// elements from the base pointer) is a multiple of the 16-byte vector.
+static bool affine_k_blocks(const std::vector<int64_t>& rows, int64_t nrows, const std::vector<int64_t>& ks,
+                            int64_t K, int bk, const std::vector<int64_t>& batch, int64_t L, int64_t vk) {
+  if (K < 1) return false;
+  for (int64_t b = 0; b < K; b += bk) {
+    const int64_t s0 = ks[(size_t)b];
+    if (s0 % vk) return false;
+    for (int64_t k = b + 1; k < std::min<int64_t>(K, b + bk); ++k)
+      if (ks[(size_t)k] != s0 + (k - b)) return false;
+  }
+  for (int64_t m = 0; m < nrows; ++m)
+    if (rows[(size_t)m] % vk) return false;
+  for (int64_t l = 0; l < L; ++l)
+    if (batch[(size_t)l] % vk) return false;
+  return true;
+}
+
+// Affine-block flags of X and Y for a plan with K-slice depth bk (32-bit
+// offsets and the native compute mode only); v holds the nine indexing
+// vectors in upload() order.
+static void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int64_t>* v, bool* xv,
+                      bool* yv) {
+  *xv = *yv = false;
+  if (index_bits != 32 || split_parts(an.compute) != 0) return;
+  const int64_t vk = 16 / an.esize;
+  *xv = an.x_kfast && affine_k_blocks(v[0], an.M, v[1], an.K, bk, v[6], an.L, vk);
+  *yv = an.y_kfast && affine_k_blocks(v[3], an.N, v[2], an.K, bk, v[7], an.L, vk);
+}
+
+static void all_offsets(const Analysis& an, std::vector<int64_t>* v) {
+  const std::vector<Mode>* groups[9] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J, &an.Lm, &an.Lm, &an.Lm};
+  const int which[9] = {0, 0, 1, 1, 2, 2, 0, 1, 2};
+  const int64_t len[9] = {an.M, an.K, an.K, an.N, an.M, an.N, an.L, an.L, an.L};
+  for (int i = 0; i < 9; ++i) offsets(*groups[i], which[i], len[i], len[i], v[i]);
+}
+
 template <typename OffT>
 static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp) {
   const Analysis& an = p->an;
@@ -173,6 +213,7 @@ static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t 
   offsets(an.Lm, 2, an.L, an.L, v[8]);
   const bool bytes = sizeof(OffT) == 4;
   const int64_t es = an.esize;
+  vec_flags(an, p->cfg.bk, bytes ? 32 : 64, v, &p->x_vec, &p->y_vec);
   const int64_t shift[6] = {an.x_lo, 0, 0, an.y_lo, an.c_lo_mn, 0};
   size_t n6 = 0;
   for (int i = 0; i < 6; ++i) n6 += v[i].size();
@@ -372,19 +413,22 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, 
   TileCfg t = choose_tiles(nullptr, an);
   int kchunk = 0;
   finalize_split(&t, an.K, &kchunk);
-  fill_info(an, t, index_bits_for(an), 0, info);
+  const int ib = index_bits_for(an);
+  std::vector<int64_t> v[9];
+  bool xv = false, yv = false;
+  if (an.M > 0 && an.N > 0 && (offs || ib == 32)) {
+    all_offsets(an, v);
+    vec_flags(an, t.bk, ib, v, &xv, &yv);
+  }
+  fill_info(an, t, ib, 1 + split_parts(an.compute) + (xv ? 16 : 0) + (yv ? 32 : 0), info);
   if (offs) {
     const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N + 3 * an.L;
     if (offs_len < need) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: offsets buffer too short");
-    std::vector<int64_t> v;
+    if (an.M == 0 || an.N == 0) all_offsets(an, v);
     int64_t pos = 0;
-    const std::vector<Mode>* groups[9] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J, &an.Lm, &an.Lm, &an.Lm};
-    const int which[9] = {0, 0, 1, 1, 2, 2, 0, 1, 2};
-    const int64_t len[9] = {an.M, an.K, an.K, an.N, an.M, an.N, an.L, an.L, an.L};
     for (int i = 0; i < 9; ++i) {
-      offsets(*groups[i], which[i], len[i], len[i], v);
-      std::copy(v.begin(), v.end(), offs + pos);
-      pos += len[i];
+      std::copy(v[i].begin(), v[i].end(), offs + pos);
+      pos += (int64_t)v[i].size();
     }
   }
   return FAMLIES_OK;
@@ -406,7 +450,8 @@ famlies_status famlies_plan_destroy(famlies_plan p) {
 
 famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info* info) {
   if (!p || !is_live(p) || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
-  fill_info(p->an, p->cfg, p->index_bits, 1 + split_parts(p->an.compute), info);
+  fill_info(p->an, p->cfg, p->index_bits,
+            1 + split_parts(p->an.compute) + (p->x_vec ? 16 : 0) + (p->y_vec ? 32 : 0), info);
   return FAMLIES_OK;
 }
 
@@ -457,8 +502,9 @@ static famlies_status execute_impl(famlies_plan p, double alpha, const void* A, 
   L.bm = p->cfg.bm;
   L.bn = p->cfg.bn;
   L.bk = p->cfg.bk;
-  L.xm = xp ? 2 : (an.x_kfast ? 1 : 0);
-  L.ym = yp ? 2 : (an.y_kfast ? 1 : 0);
+  // affine-block 16-byte loads need a 16-byte aligned base pointer
+  L.xm = xp ? 2 : (an.x_kfast ? (p->x_vec && !((uintptr_t)x & 15) ? 3 : 1) : 0);
+  L.ym = yp ? 2 : (an.y_kfast ? (p->y_vec && !((uintptr_t)y & 15) ? 3 : 1) : 0);
   L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
   hipError_t e;
   const int ns = split_parts(an.compute);

@@ -265,10 +265,69 @@ struct PackedGather {
   }
 };
 
-// Operand loaders by mode: 0 row-gathered, 1 K-gathered, 2 pre-packed.
-enum { kRowGather = 0, kKGather = 1, kPacked = 2 };
+// Loader for a K-gathered operand stored in affine blocks (the block-scatter
+// layout's block strides, Approach, "Supporting tensor computations"): in
+// every BK-slice of K the indexing vector is a progression of step one
+// element, and every run start is 16-byte aligned, so a row's slice is a
+// contiguous run in memory.  Each thread reads VK consecutive k's of a row
+// with one 16-byte load instead of VK gathered loads and takes one offset per
+// slice; the slice that crosses kend loads element by element and
+// zero-fills.  32-bit byte offsets only.
+template <typename T, typename OffT, int BR, int BK, int NSLOT = 1>
+struct VecKGather {
+  static_assert(sizeof(OffT) == 4, "affine-block loads use 32-bit byte offsets");
+  static constexpr int VK = 16 / (int)sizeof(T);
+  static constexpr int LDK = BK + VK;
+  static constexpr int KT = BK / VK;           // threads along k
+  static constexpr int RSTEP = kThreads / KT;  // rows between a thread's runs
+  static constexpr int NR = BR / RSTEP;        // runs per thread
+  static_assert(BK % VK == 0 && kThreads % KT == 0 && BR % RSTEP == 0, "tile shape does not divide the workgroup");
+  typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+  OffT mn[NR];
+  OffT ko[NSLOT];
+  int ks[NSLOT];
+  vec_t v[NSLOT][NR];
+  int r0 = 0, kk0 = 0, kend = 0;
+
+  __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
+    kk0 = (tid % KT) * VK;
+    r0 = tid / KT;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) mn[i] = mnoff[tile_r0 + r0 + i * RSTEP];
+  }
+  template <int S = 0>
+  __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
+    ko[S] = koff[k0 + kk0];
+    ks[S] = k0;
+  }
+  template <int S = 0>
+  __device__ __forceinline__ void load(const T* __restrict__ base) {
+    if (ks[S] + BK <= kend) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) v[S][i] = *global(reinterpret_cast<const vec_t*>(at(base, (OffT)(mn[i] + ko[S]))));
+    } else {
+      // inside a block the run continues at consecutive addresses
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int u = 0; u < VK; ++u)
+          v[S][i][u] = ks[S] + kk0 + u < kend ? gload(base, (OffT)(mn[i] + ko[S] + u * (int)sizeof(T))) : T(0);
+    }
+  }
+  template <int S = 0>
+  __device__ __forceinline__ void store(T* __restrict__ lds, int /*k0*/, int /*kend*/) const {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) *reinterpret_cast<vec_t*>(lds + (r0 + i * RSTEP) * LDK + kk0) = v[S][i];
+  }
+};
+
+// Operand loaders by mode: 0 row-gathered, 1 K-gathered, 2 pre-packed,
+// 3 K-gathered from affine unit-stride blocks.
+enum { kRowGather = 0, kKGather = 1, kPacked = 2, kVecK = 3 };
 template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1, int NSLOT = 1>
-using Loader = typename std::conditional<MODE == kPacked, PackedGather<T, BR, BK, NSLOT>,
-                                         TileGather<T, OffT, BR, BK, MODE == kKGather, KV, NSLOT>>::type;
+using Loader = typename std::conditional<
+    MODE == kPacked, PackedGather<T, BR, BK, NSLOT>,
+    typename std::conditional<MODE == kVecK, VecKGather<T, OffT, BR, BK, NSLOT>,
+                              TileGather<T, OffT, BR, BK, MODE == kKGather, KV, NSLOT>>::type>::type;
 
 }  // namespace famlies

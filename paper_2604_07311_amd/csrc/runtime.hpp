@@ -53,6 +53,9 @@ struct famlies_plan_s {
   void* d_off = nullptr;   // six OffT indexing vectors, then three int64 batch vectors
   size_t batch_off_bytes = 0;
   size_t off_pos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // X / Y are K-gathered from affine unit-stride K blocks with 16-byte
+  // aligned run starts (given a 16-byte aligned base pointer)
+  bool x_vec = false, y_vec = false;
   void* d_work = nullptr;  // split-K partial sums
   size_t work_bytes = 0;
   famlies::BatchPlan* batch = nullptr;  // set for batched plans

@@ -31,7 +31,7 @@ struct TileJob {
   int x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y
 };
 
-// XM, YM: operand loader modes (kRowGather, kKGather, kPacked).  DEPTH: K
+// XM, YM: operand loader modes (kRowGather, kKGather, kPacked, kVecK).  DEPTH: K
 // slices whose data loads are in flight while a slice is multiplied (1: the
 // next slice; 2: the next two, for latency-bound gathers when registers
 // allow).
@@ -85,6 +85,8 @@ struct PlainTile {
     gy.init(j.ymn, j.n0, tid);
     if constexpr (XM == kPacked) gx.nkb = j.x_nkb;
     if constexpr (YM == kPacked) gy.nkb = j.y_nkb;
+    if constexpr (XM == kVecK) gx.kend = j.kend;
+    if constexpr (YM == kVecK) gy.kend = j.kend;
 
     typename MF::Acc acc[MB][NB];
 #pragma unroll

@@ -193,6 +193,37 @@ def test_cost_model_orders_rows_by_the_gathered_operand(fm, oracle_lib):
     np.testing.assert_array_equal(out, want)
 
 
+def _mk(labels, ext, orders):
+    lays = [synth.layout([ext[ch] for ch in lab], order=o) for lab, o in zip(labels, orders)]
+    return synth.Problem("affine", *labels, *lays, 1.0, 0.5)
+
+
+def test_affine_block_flags(fm):
+    """Block strides: the plan reads an operand with 16-byte loads (kernel id
+    +16 for X, +32 for Y) exactly when it is K-gathered, each K-slice of its
+    indexing vector steps by one element, and every run start is a multiple
+    of the 16-byte vector (2 FP64 or 4 FP32 elements)."""
+    F64, F32 = fm.FAMLIES_F64, fm.FAMLIES_F32
+    lad = synth.ladder(32, 4, seed=1)           # W stored (e,a,f,b): K blocks inside e
+    for dt in (F64, F32):
+        info, _ = analyze(fm, lad, dt)
+        assert info["kernel"] == 1 + 16 + 32
+    rows30 = _mk(("ki", "kj", "ji"), {"k": 30, "i": 20, "j": 6}, (None, None, None))
+    assert analyze(fm, rows30, F64)[0]["kernel"] == 49      # 30 % 2 == 0
+    assert analyze(fm, rows30, F32)[0]["kernel"] == 1       # 30 % 4 != 0
+    # K modes that do not fuse and a K extent that splits the 32-wide slices
+    split = _mk(("kil", "klj", "ij"), {"k": 40, "l": 3, "i": 20, "j": 8}, ([0, 1, 2], [0, 2, 1], [0, 1]))
+    info, _ = analyze(fm, split, F32)
+    assert info["kernel"] & 48 == 0
+    info, _ = analyze(fm, split, F64)                       # 16-wide slices: 40 = 16+16+8 still splits
+    assert info["kernel"] & 48 == 0
+    # a row-gathered operand never takes the flag; the split precisions never do
+    ring = synth.ring(4, 8, seed=1)
+    info, _ = analyze(fm, ring, F32)
+    assert info["y_kfast"] == 0 and not info["kernel"] & 32
+    assert analyze(fm, lad, F32, compute=1)[0]["kernel"] == 3
+
+
 def test_negative_and_zero_strides_offsets(fm):
     a = synth.layout([3, 4], negate=[True, False])
     b = synth.layout([4, 5], zero=[False, True])
