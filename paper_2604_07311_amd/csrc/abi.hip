@@ -180,12 +180,11 @@ static bool affine_k_blocks(const std::vector<int64_t>& rows, int64_t nrows, con
 }
 
 // Affine-block flags of X and Y for a plan with K-slice depth bk (32-bit
-// offsets and the native compute mode only); v holds the nine indexing
-// vectors in upload() order.
+// offsets only); v holds the nine indexing vectors in upload() order.
 static void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int64_t>* v, bool* xv,
                       bool* yv) {
   *xv = *yv = false;
-  if (index_bits != 32 || split_parts(an.compute) != 0) return;
+  if (index_bits != 32) return;
   const int64_t vk = 16 / an.esize;
   *xv = an.x_kfast && affine_k_blocks(v[0], an.M, v[1], an.K, bk, v[6], an.L, vk);
   *yv = an.y_kfast && affine_k_blocks(v[3], an.N, v[2], an.K, bk, v[7], an.L, vk);

@@ -324,7 +324,13 @@ struct VecKGather {
 // Operand loaders by mode: 0 row-gathered, 1 K-gathered, 2 pre-packed,
 // 3 K-gathered from affine unit-stride blocks.
 enum { kRowGather = 0, kKGather = 1, kPacked = 2, kVecK = 3 };
-template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1, int NSLOT = 1>
+template <int MODE>
+constexpr bool known_mode() {
+  static_assert(MODE >= kRowGather && MODE <= kVecK, "unknown loader mode");
+  return true;
+}
+template <typename T, typename OffT, int BR, int BK, int MODE, int KV = 1, int NSLOT = 1,
+          bool = known_mode<MODE>()>
 using Loader = typename std::conditional<
     MODE == kPacked, PackedGather<T, BR, BK, NSLOT>,
     typename std::conditional<MODE == kVecK, VecKGather<T, OffT, BR, BK, NSLOT>,

@@ -82,11 +82,13 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
 // bf16, [row][k], zero-filled past the edges; see famlies_pack).
 template <typename OffT, int BR, int NS, int MODE>
 struct SplitLoader {
+  static_assert(MODE == kRowGather || MODE == kKGather, "every other mode has its own loader");
   static constexpr bool KF = MODE == kKGather;
   using G = TileGather<float, OffT, BR, kB3K, KF, KF ? 2 : 1>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
+  __device__ __forceinline__ void set_kend(int) {}
   __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
   __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int k0, int kend) const {
@@ -94,6 +96,42 @@ struct SplitLoader {
       store_split<NS, G, KF, false>(g, tiles, tile_elems, k0, kend);
     else
       store_split<NS, G, KF, true>(g, tiles, tile_elems, k0, kend);
+  }
+};
+
+// Four consecutive k's of one row, split and written as 8-byte runs of
+// bf16 per part (t-th part at tiles + t * tile_elems + idx).
+template <int NS>
+__device__ __forceinline__ void store_split4(float x0, float x1, float x2, float x3, __bf16* tiles, int tile_elems,
+                                             int idx) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  uint32_t p0[NS], p1[NS];
+  split2<NS>(x0, x1, p0);
+  split2<NS>(x2, x3, p1);
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const u32x2 w = {p0[t], p1[t]};
+    *reinterpret_cast<u32x2*>(tiles + t * tile_elems + idx) = w;
+  }
+}
+
+// K-gathered from affine unit-stride K blocks: 16-byte loads of four k's
+// (the loads zero-fill past kend).
+template <typename OffT, int BR, int NS>
+struct SplitLoader<OffT, BR, NS, kVecK> {
+  using G = VecKGather<float, OffT, BR, kB3K>;
+  G g;
+  int nkb = 0;
+  __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
+  __device__ __forceinline__ void set_kend(int kend) { g.kend = kend; }
+  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
+  __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
+  __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {
+#pragma unroll
+    for (int i = 0; i < G::NR; ++i) {
+      const auto v = g.v[0][i];
+      store_split4<NS>(v[0], v[1], v[2], v[3], tiles, tile_elems, (g.r0 + i * G::RSTEP) * kB3LD + g.kk0);
+    }
   }
 };
 
@@ -108,6 +146,7 @@ struct SplitLoader<OffT, BR, NS, kPacked> {
     tile = tile_r0 / BR;
     tid = t;
   }
+  __device__ __forceinline__ void set_kend(int) {}
   __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb = k0 / kB3K; }
   __device__ __forceinline__ void load(const void* base) {
     const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb) * (size_t)(NS * BR * kB3K);
@@ -169,6 +208,8 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   gy.init(a.ymn, n0, tid);
   gx.nkb = a.x_nkb;
   gy.nkb = a.y_nkb;
+  gx.set_kend(kend);
+  gy.set_kend(kend);
 
   f32x16 acc[NS][MB][NB];  // acc[o]: products whose parts' orders sum to o
 #pragma unroll
@@ -298,25 +339,32 @@ static void launch_split_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) 
   hipLaunchKernelGGL((split_contract<OffT, BM, BN, XM, YM, NS>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered operands with either offset width; pre-packed operands with
-// 32-bit offsets only.
+// Gathered operands with either offset width; pre-packed operands and
+// affine K blocks with 32-bit offsets only.
 template <typename OffT, int BM, int BN, int NS>
 static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
-  const int code = xm * 3 + ym;
+  const int code = xm * 4 + ym;
   switch (code) {
     case 0: launch_split_one<OffT, BM, BN, NS, 0, 0>(a, grid, s); return hipGetLastError();
     case 1: launch_split_one<OffT, BM, BN, NS, 0, 1>(a, grid, s); return hipGetLastError();
-    case 3: launch_split_one<OffT, BM, BN, NS, 1, 0>(a, grid, s); return hipGetLastError();
-    case 4: launch_split_one<OffT, BM, BN, NS, 1, 1>(a, grid, s); return hipGetLastError();
+    case 4: launch_split_one<OffT, BM, BN, NS, 1, 0>(a, grid, s); return hipGetLastError();
+    case 5: launch_split_one<OffT, BM, BN, NS, 1, 1>(a, grid, s); return hipGetLastError();
     default: break;
   }
   if constexpr (sizeof(OffT) == 4) {
     switch (code) {
       case 2: launch_split_one<OffT, BM, BN, NS, 0, 2>(a, grid, s); return hipGetLastError();
-      case 5: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();
-      case 6: launch_split_one<OffT, BM, BN, NS, 2, 0>(a, grid, s); return hipGetLastError();
-      case 7: launch_split_one<OffT, BM, BN, NS, 2, 1>(a, grid, s); return hipGetLastError();
-      case 8: launch_split_one<OffT, BM, BN, NS, 2, 2>(a, grid, s); return hipGetLastError();
+      case 3: launch_split_one<OffT, BM, BN, NS, 0, 3>(a, grid, s); return hipGetLastError();
+      case 6: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();
+      case 7: launch_split_one<OffT, BM, BN, NS, 1, 3>(a, grid, s); return hipGetLastError();
+      case 8: launch_split_one<OffT, BM, BN, NS, 2, 0>(a, grid, s); return hipGetLastError();
+      case 9: launch_split_one<OffT, BM, BN, NS, 2, 1>(a, grid, s); return hipGetLastError();
+      case 10: launch_split_one<OffT, BM, BN, NS, 2, 2>(a, grid, s); return hipGetLastError();
+      case 11: launch_split_one<OffT, BM, BN, NS, 2, 3>(a, grid, s); return hipGetLastError();
+      case 12: launch_split_one<OffT, BM, BN, NS, 3, 0>(a, grid, s); return hipGetLastError();
+      case 13: launch_split_one<OffT, BM, BN, NS, 3, 1>(a, grid, s); return hipGetLastError();
+      case 14: launch_split_one<OffT, BM, BN, NS, 3, 2>(a, grid, s); return hipGetLastError();
+      case 15: launch_split_one<OffT, BM, BN, NS, 3, 3>(a, grid, s); return hipGetLastError();
       default: break;
     }
   }

@@ -217,11 +217,12 @@ def test_affine_block_flags(fm):
     assert info["kernel"] & 48 == 0
     info, _ = analyze(fm, split, F64)                       # 16-wide slices: 40 = 16+16+8 still splits
     assert info["kernel"] & 48 == 0
-    # a row-gathered operand never takes the flag; the split precisions never do
+    # a row-gathered operand never takes the flag; the split precisions do
     ring = synth.ring(4, 8, seed=1)
     info, _ = analyze(fm, ring, F32)
     assert info["y_kfast"] == 0 and not info["kernel"] & 32
-    assert analyze(fm, lad, F32, compute=1)[0]["kernel"] == 3
+    assert analyze(fm, lad, F32, compute=1)[0]["kernel"] == 3 + 48
+    assert analyze(fm, lad, F32, compute=2)[0]["kernel"] == 4 + 48
 
 
 def test_negative_and_zero_strides_offsets(fm):
