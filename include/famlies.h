@@ -223,7 +223,13 @@ famlies_status famlies_network_destroy(famlies_network n);
  * (text, one line per class); the handle then uses it.  flags: bit 0 = quick
  * (fewer repetitions). */
 famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags);
-/* Load a table written by famlies_tune. */
+/* Load a table written by famlies_tune (or by hand).  Text, '#' comments,
+ * one entry per line:
+ *   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits>]
+ * A plan takes the entry of its size class (or the nearest one within two
+ * classes).  The optional last field 64 makes such plans use 64-bit indexing
+ * vectors even when 32 bits reach every element.  Errors: INVALID_ARG for an
+ * unreadable or malformed file (the handle's table is then unchanged). */
 famlies_status famlies_load_tune_table(famlies_handle h, const char *table_path);
 
 const char *famlies_last_error(void);

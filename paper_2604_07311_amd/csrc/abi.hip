@@ -299,8 +299,8 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
   p->h = h;
   p->an = an;
-  p->index_bits = index_bits_for(an);
   p->cfg = force ? *force : choose_tiles(h, an);
+  p->index_bits = p->cfg.index_bits == 64 ? 64 : index_bits_for(an);
   const int ns = split_parts(compute);
   if (ns) {
     p->cfg.bk = 32;

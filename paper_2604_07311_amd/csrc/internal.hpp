@@ -64,6 +64,7 @@ void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad
 struct TileCfg {
   int bm = 128, bn = 128, bk = 16;
   int split = 1;
+  int index_bits = 0;  // 64: use 64-bit indexing vectors even where 32 bits reach (0: automatic)
 };
 
 void set_error(const std::string& msg);

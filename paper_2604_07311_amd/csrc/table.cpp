@@ -49,7 +49,9 @@ void TileTable::put(const Entry& e) {
 }
 
 // Format: '#' comments; one entry per line:
-//   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split>
+//   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits>]
+// where the optional last field 64 makes plans of that class use 64-bit
+// indexing vectors even when 32 bits reach every element.
 bool TileTable::load(const std::string& path, std::string* err) {
   std::ifstream f(path);
   if (!f) {
@@ -72,6 +74,14 @@ bool TileTable::load(const std::string& path, std::string* err) {
       *err = path + ":" + std::to_string(ln) + ": malformed entry";
       return false;
     }
+    int bits = 0;
+    if (is >> bits) {
+      if (bits != 0 && bits != 32 && bits != 64) {
+        *err = path + ":" + std::to_string(ln) + ": index bits must be 32 or 64";
+        return false;
+      }
+      e.cfg.index_bits = bits == 64 ? 64 : 0;
+    }
     e.kind = kind == "plain" ? 0 : 1;
     got.push_back(e);
   }
@@ -85,11 +95,14 @@ bool TileTable::save(const std::string& path, std::string* err) const {
     *err = "cannot write " + path;
     return false;
   }
-  f << "# famlies tile table: kind dtype compute log2M log2N log2K bm bn bk split\n";
-  for (const Entry& e : entries)
+  f << "# famlies tile table: kind dtype compute log2M log2N log2K bm bn bk split [index_bits]\n";
+  for (const Entry& e : entries) {
     f << (e.kind == 0 ? "plain" : "batch") << ' ' << e.dtype << ' ' << e.compute << ' ' << e.lm << ' '
       << e.ln << ' ' << e.lk << ' ' << e.cfg.bm << ' ' << e.cfg.bn << ' ' << e.cfg.bk << ' '
-      << e.cfg.split << '\n';
+      << e.cfg.split;
+    if (e.cfg.index_bits) f << ' ' << e.cfg.index_bits;
+    f << '\n';
+  }
   return (bool)f;
 }
 
