@@ -1,6 +1,6 @@
 """Benchmark: strided tensor contraction on one MI355X.
 
-Workloads (synthetic, seeded; see the design doc for the recipes):
+Workloads (synthetic, seeded):
   ladder    (default) C[a,b,i,j] += sum_{e,f} W[a,b,e,f] T[e,f,i,j], v=128, o=32,
             W stored in mode order (e,a,f,b); FP64 headline, FP32 secondary.
   ladder3   the same ladder at v=192, o=48 with outliers: FP32 vs bf16x3.
@@ -636,8 +636,8 @@ def main():
                          "reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (how the "
-              "contraction would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run it "
+              "with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"

@@ -59,7 +59,7 @@ typedef int32_t famlies_status;
 #define FAMLIES_ERR_INVALID_ARG (-1)    /* null pointer, rank < 0 or > 8, negative extent, bad enum */
 #define FAMLIES_ERR_SHAPE_MISMATCH (-2) /* one label with two different extents */
 #define FAMLIES_ERR_LABEL (-3)          /* C label in neither A nor B, or repeated in C */
-#define FAMLIES_ERR_UNSUPPORTED (-4)    /* valid input this build does not run (see each call) */
+#define FAMLIES_ERR_UNSUPPORTED (-4)    /* valid input the library does not run (see each call) */
 #define FAMLIES_ERR_ALIAS (-5)          /* C not injective, or C's span overlaps A's/B's */
 #define FAMLIES_ERR_ALIGN (-6)          /* data pointer not aligned to its element size */
 #define FAMLIES_ERR_ALLOC (-7)          /* device allocation failed */

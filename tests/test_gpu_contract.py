@@ -267,3 +267,27 @@ def test_batch_mode_real(gpu, dtype):
     p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
     note("batch mode %s" % dtype)
     _parity(gpu, p, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rank8_tensors(gpu, dtype):
+    """The largest rank the interface takes: A, B and C of rank 8 (four row,
+    four contracted and four column labels), permuted and padded storage,
+    integer data, so the result is exact."""
+    rng = np.random.default_rng(777)
+    I, P, J = "abcd", "efgh", "ijkl"
+    ext = {ch: int(rng.integers(2, 4)) for ch in I + P + J}
+
+    def lay(labels):
+        order = list(rng.permutation(len(labels)))
+        pad = [int(rng.integers(0, 2)) for _ in labels]
+        return synth.layout([ext[ch] for ch in labels], order=order, pad=pad)
+
+    la, lb, lc = I[:2] + P + I[2:], P[::-1] + J, J[:2] + I + J[2:]
+    p = synth.Problem("rank8", la, lb, lc, lay(la), lay(lb), lay(lc), 1.0, 0.5)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    note("rank-8 %s: %s" % (dtype, synth.sizes(p)))
+    want = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    got = gpu.run(p, dtype)
+    used = used_offsets(p.c)
+    np.testing.assert_array_equal(got[used], want[used])
