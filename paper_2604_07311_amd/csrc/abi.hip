@@ -179,12 +179,11 @@ static bool affine_k_blocks(const std::vector<int64_t>& rows, int64_t nrows, con
   return true;
 }
 
-// Affine-block flags of X and Y for a plan with K-slice depth bk (32-bit
-// offsets only); v holds the nine indexing vectors in upload() order.
-static void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int64_t>* v, bool* xv,
+// Affine-block flags of X and Y for a plan with K-slice depth bk; v holds
+// the nine indexing vectors in upload() order.
+static void vec_flags(const Analysis& an, int bk, int /*index_bits*/, const std::vector<int64_t>* v, bool* xv,
                       bool* yv) {
   *xv = *yv = false;
-  if (index_bits != 32) return;
   const int64_t vk = 16 / an.esize;
   *xv = an.x_kfast && affine_k_blocks(v[0], an.M, v[1], an.K, bk, v[6], an.L, vk);
   *yv = an.y_kfast && affine_k_blocks(v[3], an.N, v[2], an.K, bk, v[7], an.L, vk);
@@ -415,7 +414,7 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, 
   const int ib = index_bits_for(an);
   std::vector<int64_t> v[9];
   bool xv = false, yv = false;
-  if (an.M > 0 && an.N > 0 && (offs || ib == 32)) {
+  if (an.M > 0 && an.N > 0) {
     all_offsets(an, v);
     vec_flags(an, t.bk, ib, v, &xv, &yv);
   }

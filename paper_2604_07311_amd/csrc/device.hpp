@@ -272,11 +272,12 @@ struct PackedGather {
 // contiguous run in memory.  Each thread reads VK consecutive k's of a row
 // with one 16-byte load instead of VK gathered loads and takes one offset per
 // slice; the slice that crosses kend loads element by element and
-// zero-fills.  32-bit byte offsets only.
+// zero-fills.
 template <typename T, typename OffT, int BR, int BK, int NSLOT = 1>
 struct VecKGather {
-  static_assert(sizeof(OffT) == 4, "affine-block loads use 32-bit byte offsets");
   static constexpr int VK = 16 / (int)sizeof(T);
+  // one element in offset units: bytes for 32-bit offsets, elements for 64-bit ones
+  static constexpr int kStep = sizeof(OffT) == 4 ? (int)sizeof(T) : 1;
   static constexpr int LDK = BK + VK;
   static constexpr int KT = BK / VK;           // threads along k
   static constexpr int RSTEP = kThreads / KT;  // rows between a thread's runs
@@ -311,7 +312,7 @@ struct VecKGather {
       for (int i = 0; i < NR; ++i)
 #pragma unroll
         for (int u = 0; u < VK; ++u)
-          v[S][i][u] = ks[S] + kk0 + u < kend ? gload(base, (OffT)(mn[i] + ko[S] + u * (int)sizeof(T))) : T(0);
+          v[S][i][u] = ks[S] + kk0 + u < kend ? gload(base, (OffT)(mn[i] + ko[S] + u * kStep)) : T(0);
     }
   }
   template <int S = 0>

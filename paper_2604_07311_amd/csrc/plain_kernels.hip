@@ -112,30 +112,30 @@ static void launch_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) {
 // operands (mode 2) with 32-bit offsets only.
 template <typename T, typename OffT, int BM, int BN, int BK>
 static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
-  // gathered modes for every offset width; pre-packed and affine-block modes
-  // with 32-bit offsets only
+  // gathered and affine-block modes for every offset width; pre-packed
+  // operands with 32-bit offsets only
   const int code = xm * 4 + ym;
   switch (code) {
     case 0: launch_one<T, OffT, BM, BN, BK, 0, 0>(a, grid, s); return hipGetLastError();
     case 1: launch_one<T, OffT, BM, BN, BK, 0, 1>(a, grid, s); return hipGetLastError();
+    case 3: launch_one<T, OffT, BM, BN, BK, 0, 3>(a, grid, s); return hipGetLastError();
     case 4: launch_one<T, OffT, BM, BN, BK, 1, 0>(a, grid, s); return hipGetLastError();
     case 5: launch_one<T, OffT, BM, BN, BK, 1, 1>(a, grid, s); return hipGetLastError();
+    case 7: launch_one<T, OffT, BM, BN, BK, 1, 3>(a, grid, s); return hipGetLastError();
+    case 12: launch_one<T, OffT, BM, BN, BK, 3, 0>(a, grid, s); return hipGetLastError();
+    case 13: launch_one<T, OffT, BM, BN, BK, 3, 1>(a, grid, s); return hipGetLastError();
+    case 15: launch_one<T, OffT, BM, BN, BK, 3, 3>(a, grid, s); return hipGetLastError();
     default: break;
   }
   if constexpr (sizeof(OffT) == 4) {
     switch (code) {
       case 2: launch_one<T, OffT, BM, BN, BK, 0, 2>(a, grid, s); return hipGetLastError();
-      case 3: launch_one<T, OffT, BM, BN, BK, 0, 3>(a, grid, s); return hipGetLastError();
       case 6: launch_one<T, OffT, BM, BN, BK, 1, 2>(a, grid, s); return hipGetLastError();
-      case 7: launch_one<T, OffT, BM, BN, BK, 1, 3>(a, grid, s); return hipGetLastError();
       case 8: launch_one<T, OffT, BM, BN, BK, 2, 0>(a, grid, s); return hipGetLastError();
       case 9: launch_one<T, OffT, BM, BN, BK, 2, 1>(a, grid, s); return hipGetLastError();
       case 10: launch_one<T, OffT, BM, BN, BK, 2, 2>(a, grid, s); return hipGetLastError();
       case 11: launch_one<T, OffT, BM, BN, BK, 2, 3>(a, grid, s); return hipGetLastError();
-      case 12: launch_one<T, OffT, BM, BN, BK, 3, 0>(a, grid, s); return hipGetLastError();
-      case 13: launch_one<T, OffT, BM, BN, BK, 3, 1>(a, grid, s); return hipGetLastError();
       case 14: launch_one<T, OffT, BM, BN, BK, 3, 2>(a, grid, s); return hipGetLastError();
-      case 15: launch_one<T, OffT, BM, BN, BK, 3, 3>(a, grid, s); return hipGetLastError();
       default: break;
     }
   }

@@ -339,32 +339,32 @@ static void launch_split_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) 
   hipLaunchKernelGGL((split_contract<OffT, BM, BN, XM, YM, NS>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered operands with either offset width; pre-packed operands and
-// affine K blocks with 32-bit offsets only.
+// Gathered and affine-block operands with either offset width; pre-packed
+// operands with 32-bit offsets only.
 template <typename OffT, int BM, int BN, int NS>
 static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
   const int code = xm * 4 + ym;
   switch (code) {
     case 0: launch_split_one<OffT, BM, BN, NS, 0, 0>(a, grid, s); return hipGetLastError();
     case 1: launch_split_one<OffT, BM, BN, NS, 0, 1>(a, grid, s); return hipGetLastError();
+    case 3: launch_split_one<OffT, BM, BN, NS, 0, 3>(a, grid, s); return hipGetLastError();
     case 4: launch_split_one<OffT, BM, BN, NS, 1, 0>(a, grid, s); return hipGetLastError();
     case 5: launch_split_one<OffT, BM, BN, NS, 1, 1>(a, grid, s); return hipGetLastError();
+    case 7: launch_split_one<OffT, BM, BN, NS, 1, 3>(a, grid, s); return hipGetLastError();
+    case 12: launch_split_one<OffT, BM, BN, NS, 3, 0>(a, grid, s); return hipGetLastError();
+    case 13: launch_split_one<OffT, BM, BN, NS, 3, 1>(a, grid, s); return hipGetLastError();
+    case 15: launch_split_one<OffT, BM, BN, NS, 3, 3>(a, grid, s); return hipGetLastError();
     default: break;
   }
   if constexpr (sizeof(OffT) == 4) {
     switch (code) {
       case 2: launch_split_one<OffT, BM, BN, NS, 0, 2>(a, grid, s); return hipGetLastError();
-      case 3: launch_split_one<OffT, BM, BN, NS, 0, 3>(a, grid, s); return hipGetLastError();
       case 6: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();
-      case 7: launch_split_one<OffT, BM, BN, NS, 1, 3>(a, grid, s); return hipGetLastError();
       case 8: launch_split_one<OffT, BM, BN, NS, 2, 0>(a, grid, s); return hipGetLastError();
       case 9: launch_split_one<OffT, BM, BN, NS, 2, 1>(a, grid, s); return hipGetLastError();
       case 10: launch_split_one<OffT, BM, BN, NS, 2, 2>(a, grid, s); return hipGetLastError();
       case 11: launch_split_one<OffT, BM, BN, NS, 2, 3>(a, grid, s); return hipGetLastError();
-      case 12: launch_split_one<OffT, BM, BN, NS, 3, 0>(a, grid, s); return hipGetLastError();
-      case 13: launch_split_one<OffT, BM, BN, NS, 3, 1>(a, grid, s); return hipGetLastError();
       case 14: launch_split_one<OffT, BM, BN, NS, 3, 2>(a, grid, s); return hipGetLastError();
-      case 15: launch_split_one<OffT, BM, BN, NS, 3, 3>(a, grid, s); return hipGetLastError();
       default: break;
     }
   }

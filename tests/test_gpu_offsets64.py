@@ -47,20 +47,23 @@ def _run64(gpu, tmp_path, p, dtype, compute="native", bm=None):
     note("64-bit %s %s %s: tile %d split %d kernel %d" % (p.name, dtype, compute, info["tile_m"],
                                                         info["split_k"], info["kernel"]))
     assert info["index_bits"] == 64
-    assert info["kernel"] & 48 == 0          # no affine-block loads on this path
     got = gpu.run(p, dtype, compute=compute, plan=plan)
     gpu.fm.famlies_plan_destroy(plan)
     gpu.fm.famlies_destroy(h)
-    return got
+    return got, info
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bm", [64, 128])
-def test_ladder_64bit(gpu, tmp_path, dtype, bm):
-    p = round_inputs(synth.ladder(24, 8, seed=301), dtype)
-    got = _run64(gpu, tmp_path, p, dtype, bm=bm)
+@pytest.mark.parametrize("v", [24, 32])
+def test_ladder_64bit(gpu, tmp_path, dtype, bm, v):
+    """v = 24: only T's fused K is read in affine blocks (W's e-runs of 24
+    split the K slices); v = 32: both operands are."""
+    p = round_inputs(synth.ladder(v, 8, seed=301), dtype)
+    got, info = _run64(gpu, tmp_path, p, dtype, bm=bm)
+    assert info["kernel"] & 48 == (48 if v == 32 else 16)
     want, d = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:], want_cond=True)
-    (check_fp64 if dtype == "f64" else check_fp32)(got, want, d, 24 * 24)
+    (check_fp64 if dtype == "f64" else check_fp32)(got, want, d, v * v)
 
 
 @pytest.mark.parametrize("seed", range(4))
@@ -77,7 +80,7 @@ def test_random_general_labels_64bit(gpu, tmp_path, seed):
         q = synth.Problem(p.name, p.la, p.lb, p.lc, p.a, p.b, p.c, p.alpha, p.beta)
         q.abuf, q.bbuf, q.cbuf = p.abuf.copy(), p.bbuf.copy(), p.cbuf.copy()
         q = round_inputs(q, dtype)
-        got = _run64(gpu, tmp_path, q, dtype)
+        got, _ = _run64(gpu, tmp_path, q, dtype)
         want, d = oracle.contract(q.alpha, *q.oracle_args()[:4], q.beta, *q.oracle_args()[4:], want_cond=True)
         (check_fp64 if dtype == "f64" else check_fp32)(got, want, d, K, where=used)
 
@@ -87,7 +90,8 @@ def test_bf16x3_64bit(gpu, tmp_path):
     K = 400
     exact, d = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:], want_cond=True)
     _, dp = oracle.contract(p.alpha, *p.oracle_args()[:4], 0.0, *p.oracle_args()[4:], want_cond=True)
-    got = _run64(gpu, tmp_path, p, "f32", compute="bf16x3")
+    got, info = _run64(gpu, tmp_path, p, "f32", compute="bf16x3")
+    assert info["kernel"] & 16             # T's fused K: affine blocks on the 64-bit path
     assert np.all(np.abs(got - exact) <= bf16x3_bound(K, dp, d))
 
 
@@ -98,6 +102,6 @@ def test_batch_modes_64bit(gpu, tmp_path):
     p = synth.Problem("batch64", "ikb", "kjb", "bji", a, b, c, 1.0, 0.5)
     rng = np.random.default_rng(330)
     p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
-    got = _run64(gpu, tmp_path, p, "f64")
+    got, _ = _run64(gpu, tmp_path, p, "f64")
     want, d = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:], want_cond=True)
     check_fp64(got, want, d, 30)
