@@ -16,6 +16,11 @@ struct Mode {
   int32_t label;
   int64_t ext;
   int64_t sx, sy, sc;
+  // Blocked enumeration: when the first two modes of a group carry blk > 0,
+  // the group's index runs over blk0 x blk1 blocks of those two modes: inside
+  // a block the first mode runs fastest, then the second; the blocks follow
+  // the first mode, then the second; the remaining modes come last.
+  int64_t blk = 0;
 };
 
 // Result of steps a1-a3 (label classification, grouping/fusion, orientation,
@@ -23,8 +28,9 @@ struct Mode {
 //   C(m,n) = sum_k X(m,k) * Y(k,n)
 // with X(m,k) at x + xmn[m] + xk[k], Y(k,n) at y + yk[k] + ymn[n] and C(m,n)
 // at c + cm[m] + cn[n]; each offset vector is the column-major odometer over
-// its group's modes (first mode fastest), the same order for every operand
-// holding the group (conformal partitioning).
+// its group's modes (first mode fastest; blocked over its first two modes
+// when they carry block sizes), the same order for every operand holding the
+// group (conformal partitioning).
 //
 // Labels that are not in exactly two tensors are folded into the same view:
 // a label in all three tensors is a batch ("L") mode -- one independent GEMM

@@ -304,6 +304,31 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
   // LDS-contiguous way; an empty free group has no rows to gather along).
   an.x_kfast = !an.P.empty() && first(an.P, 0) <= first(an.I, 0);
   an.y_kfast = !an.P.empty() && first(an.P, 1) <= first(an.J, 1);
+
+  // Both operands gathered along K but fastest along different contracted
+  // modes u (of X) and w (of Y): a K slice in plain order would be one run
+  // for X and single elements for Y.  Enumerate K instead in bu x bw blocks
+  // of (u, w), so one slice holds runs of bu consecutive X elements and of bw
+  // consecutive Y elements.  The K order is shared by X and Y, so any such
+  // enumeration is valid.
+  if (an.P.size() >= 2) {
+    size_t iu = 0, iw = 0;
+    for (size_t q = 1; q < an.P.size(); ++q) {
+      if (iabs(an.P[q].sx) < iabs(an.P[iu].sx)) iu = q;
+      if (iabs(an.P[q].sy) < iabs(an.P[iw].sy)) iw = q;
+    }
+    const int64_t su = iabs(an.P[iu].sx), sw = iabs(an.P[iw].sy);
+    if (iu != iw && su >= 1 && su <= 2 && sw >= 1 && sw <= 2 && su <= first(an.I, 0) && sw <= first(an.J, 1)) {
+      std::vector<Mode> q{an.P[iu], an.P[iw]};
+      for (size_t r = 0; r < an.P.size(); ++r)
+        if (r != iu && r != iw) q.push_back(an.P[r]);
+      const int64_t bk = an.esize == 8 ? 16 : 32;
+      q[0].blk = std::min<int64_t>(q[0].ext, bk == 32 ? 8 : 4);
+      q[1].blk = std::max<int64_t>(1, std::min<int64_t>(q[1].ext, bk / q[0].blk));
+      an.P = q;
+      an.x_kfast = an.y_kfast = true;
+    }
+  }
   an.max_abs_x = reach(an.I, 0) + reach(an.P, 0) + reach(an.Lm, 0);
   an.max_abs_y = reach(an.J, 1) + reach(an.P, 1) + reach(an.Lm, 1);
   an.max_abs_c = reach(an.I, 2) + reach(an.J, 2) + reach(an.Lm, 2);
@@ -320,6 +345,25 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
 void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad,
              std::vector<int64_t>& out) {
   out.assign(static_cast<size_t>(n_pad), 0);
+  if (modes.size() >= 2 && modes[0].blk > 0 && modes[1].blk > 0) {
+    // blocked: (u in block, w in block, u block, w block, remaining modes)
+    const Mode& u = modes[0];
+    const Mode& w = modes[1];
+    const std::vector<Mode> rest(modes.begin() + 2, modes.end());
+    std::vector<int64_t> outer;
+    int64_t nrest = 1;
+    for (const Mode& m : rest) nrest *= m.ext;
+    offsets(rest, which, nrest, nrest, outer);
+    const int64_t su = sel(u, which), sw = sel(w, which);
+    int64_t i = 0;
+    for (int64_t r = 0; r < nrest && i < n; ++r)
+      for (int64_t w0 = 0; w0 < w.ext && i < n; w0 += w.blk)
+        for (int64_t u0 = 0; u0 < u.ext && i < n; u0 += u.blk)
+          for (int64_t b = w0; b < std::min(w.ext, w0 + w.blk) && i < n; ++b)
+            for (int64_t a = u0; a < std::min(u.ext, u0 + u.blk) && i < n; ++a)
+              out[static_cast<size_t>(i++)] = outer[static_cast<size_t>(r)] + a * su + b * sw;
+    return;
+  }
   std::vector<int64_t> digit(modes.size(), 0);
   int64_t off = 0;
   for (int64_t i = 0; i < n; ++i) {

@@ -225,6 +225,44 @@ def test_affine_block_flags(fm):
     assert analyze(fm, lad, F32, compute=2)[0]["kernel"] == 4 + 48
 
 
+def test_blocked_k_enumeration(fm):
+    """A is fastest along p, B along q, both contracted: K is enumerated in
+    8 x 4 (FP32) or 4 x 4 (FP64) blocks of (p, q), so every 32-wide K slice
+    holds runs of consecutive elements of both operands; the kernel view still
+    reproduces the oracle exactly."""
+    import oracle
+    ext = {"i": 20, "p": 12, "q": 10, "j": 18}
+    a = synth.layout([ext["i"], ext["p"], ext["q"]], order=[1, 0, 2])   # A[i,p,q]: p fastest
+    b = synth.layout([ext["q"], ext["p"], ext["j"]])                     # B[q,p,j]: q fastest
+    c = synth.layout([ext["j"], ext["i"]])
+    p = synth.Problem("blocked", "ipq", "qpj", "ji", a, b, c, 1.0, 0.5)
+    rng = np.random.default_rng(9)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
+    for dt, (bu, bw) in ((fm.FAMLIES_F32, (8, 4)), (fm.FAMLIES_F64, (4, 4))):
+        info, off = analyze(fm, p, dt, offsets=True)
+        assert info["x_kfast"] == 1 and info["y_kfast"] == 1
+        X, Y = (p.b, p.a) if info["swapped"] else (p.a, p.b)
+        lx, ly = ("qpj", "ipq") if info["swapped"] else ("ipq", "qpj")
+        sx = dict(zip(lx, X.strides))
+        sy = dict(zip(ly, Y.strides))
+        u = "p" if sx["p"] == 1 else "q"          # X's fastest contracted mode
+        w = "q" if u == "p" else "p"
+        want = []
+        for w0 in range(0, ext[w], bw):
+            for u0 in range(0, ext[u], bu):
+                for bb in range(w0, min(ext[w], w0 + bw)):
+                    for aa in range(u0, min(ext[u], u0 + bu)):
+                        want.append((aa, bb))
+        xk = [aa * sx[u] + bb * sx[w] for aa, bb in want]
+        yk = [aa * sy[u] + bb * sy[w] for aa, bb in want]
+        np.testing.assert_array_equal(off["xk"], xk)
+        np.testing.assert_array_equal(off["yk"], yk)
+        if dt == fm.FAMLIES_F32:
+            _, out = _kernel_view_numpy(fm, p)
+            ref = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+            np.testing.assert_array_equal(out, ref)
+
+
 def test_negative_and_zero_strides_offsets(fm):
     a = synth.layout([3, 4], negate=[True, False])
     b = synth.layout([4, 5], zero=[False, True])
