@@ -285,20 +285,41 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   };
   if (a.splits == 1) {
     float* __restrict__ C = static_cast<float*>(a.c) + a.cl[l];
+    // Every read (indexing vectors, then C for beta != 0) before the first
+    // write, so that the reads are in flight together rather than one per
+    // element; past the edge row 0 / column 0 is read and never written.
+    OffT cmv[MB][16], cnv[NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
+        cmv[i][e] = a.cm[m < a.M ? m : 0];
+      }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int n = n0 + wn * WTN + j * 32 + r;
-      const OffT cn = a.cn[n];
+      cnv[j] = a.cn[n < a.N ? n : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + wn * WTN + j * 32 + r;
+      float cv[MB][16];
+      if (a.beta != 0.0) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) cv[i][e] = *at(C, (OffT)(cmv[i][e] + cnv[j]));
+      }
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const int m = m0 + wm * WTM + i * 32 + Mfma<float>::row(lane, e);
           if (m < a.M && n < a.N) {
-            float* cp = at(C, (OffT)(a.cm[m] + cn));
             double v = a.alpha * total(i, j, e);
-            if (a.beta != 0.0) v += a.beta * (double)*cp;
-            *cp = (float)v;
+            if (a.beta != 0.0) v += a.beta * (double)cv[i][e];
+            *at(C, (OffT)(cmv[i][e] + cnv[j])) = (float)v;
           }
         }
     }

@@ -178,25 +178,47 @@ struct PlainTile {
     }
 
     if (j.work == nullptr) {
+      // Every read (the C indexing vectors, then C itself for beta != 0) is
+      // issued before the first write: a write may alias any later read as
+      // far as the compiler knows, so reads interleaved with writes would be
+      // in flight one at a time.  Rows and columns past the edge take row 0
+      // / column 0, a valid element whose value is never written back.
       T* __restrict__ C = static_cast<T*>(j.c);
       const T al = static_cast<T>(j.alpha), be = static_cast<T>(j.beta);
+      OffT cmv[MB][MF::NACC], cnv[NB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int e = 0; e < MF::NACC; ++e) {
+          const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
+          cmv[i][e] = j.cm[m < j.M ? m : 0];
+        }
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) {
         const int n = j.n0 + wn * WTN + jj * MF::BS + r;
-        const OffT cn = j.cn[n];
+        cnv[jj] = j.cn[n < j.N ? n : 0];
+      }
 #pragma unroll
-        for (int i = 0; i < MB; ++i) {
+      for (int jj = 0; jj < NB; ++jj) {
+        const int n = j.n0 + wn * WTN + jj * MF::BS + r;
+        T cv[MB][MF::NACC];
+        if (be != T(0)) {
+#pragma unroll
+          for (int i = 0; i < MB; ++i)
+#pragma unroll
+            for (int e = 0; e < MF::NACC; ++e) cv[i][e] = *global(at(C, (OffT)(cmv[i][e] + cnv[jj])));
+        }
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
 #pragma unroll
           for (int e = 0; e < MF::NACC; ++e) {
             const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
             if (m < j.M && n < j.N) {
-              auto* cp = global(at(C, (OffT)(j.cm[m] + cn)));
               T v = al * acc[i][jj][e];
-              if (be != T(0)) v += be * *cp;
-              *cp = v;
+              if (be != T(0)) v += be * cv[i][e];
+              *global(at(C, (OffT)(cmv[i][e] + cnv[jj]))) = v;
             }
           }
-        }
       }
     } else {
       T* __restrict__ W = static_cast<T*>(j.work);
