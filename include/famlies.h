@@ -113,6 +113,8 @@ typedef struct {
   int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
   int32_t kernel;           /* 1 plain, 3 bf16x3, 4 bf16x6 (1 + bf16 parts per operand); +16 / +32 when the kernel reads X / Y
                                from affine unit-stride K blocks with 16-byte loads (block strides) */
+  int32_t split_tiles;      /* split_k > 1: how many tiles run as K slices (the last ones in
+                               tile order; the others run whole first); 0 without split-K */
   double flops;             /* 2*batch*m*n*k */
 } famlies_plan_info;
 
@@ -225,11 +227,14 @@ famlies_status famlies_network_destroy(famlies_network n);
 famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags);
 /* Load a table written by famlies_tune (or by hand).  Text, '#' comments,
  * one entry per line:
- *   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits>]
+ *   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits> [<split tiles>]]
  * A plan takes the entry of its size class (or the nearest one within two
- * classes).  The optional last field 64 makes such plans use 64-bit indexing
- * vectors even when 32 bits reach every element.  Errors: INVALID_ARG for an
- * unreadable or malformed file (the handle's table is then unchanged). */
+ * classes).  The optional index bits 64 makes such plans use 64-bit indexing
+ * vectors even when 32 bits reach every element (0: automatic).  The optional
+ * split tiles n > 0 (plain FP64/FP32 plans with split > 1) cuts only the last
+ * n tiles in tile order into K slices; the others run over all of K first.
+ * Errors: INVALID_ARG for an unreadable or malformed file (the handle's table
+ * is then unchanged). */
 famlies_status famlies_load_tune_table(famlies_handle h, const char *table_path);
 
 const char *famlies_last_error(void);

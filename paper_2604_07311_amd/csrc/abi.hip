@@ -70,8 +70,13 @@ static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // the CU), so the busiest CU's time is
 //     pairs * 2w + (odd ? w / 0.65 : 0),  w = work of one workgroup,
 // a 64-edge tile does its flops at about 0.75 of the 128-edge rate, and each
-// extra K slice costs a pass over M*N partial sums (at HBM rate, measured in
-// the same units).  The model only ranks candidates; it is not a timing.
+// extra K slice costs a pass over the split tiles' partial sums (at HBM
+// rate, measured in the same units).  Splitting is either whole (every tile
+// in K slices) or of the tail only: when the tiles fill some rounds of two
+// workgroups per CU and part of one more, the whole rounds run unsplit and
+// only the tiles of the last round are cut into K slices, so that round
+// spreads over every CU instead of leaving most of them idle.  The model
+// only ranks candidates; it is not a timing.
 TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
   TileCfg t;
   const int bk = an.dtype == FAMLIES_F64 ? 16 : 32;
@@ -99,15 +104,39 @@ TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
         best = time;
         pick.bm = pick.bn = bt;
         pick.split = split;
+        pick.tail = 0;
+      }
+    }
+    // tail split: whole rounds unsplit, the last partial round in K slices
+    const int64_t slots = 2 * (int64_t)cus, rem = tiles % slots;
+    if (an.L == 1 && tiles > slots && rem > 0) {
+      const double w = 2.0 * bt * bt * (double)an.K / (cu_rate * eff);
+      const double head = (double)(tiles / slots) * 2.0 * w;
+      for (int split : {2, 3, 4, 6, 8}) {
+        if (an.K / split < 2 * bk) continue;
+        const int64_t q = ceil_div(rem * split, cus);
+        const double ws = w / split;
+        const double time = head + (double)(q / 2) * 2.0 * ws + (q % 2 ? ws / 0.65 : 0.0) +
+                            (double)split * rem * bt * bt * es * 2.0 / hbm + 4e-6;
+        if (time < best * 0.95) {  // only the tail pays for partial sums
+          best = time;
+          pick.bm = pick.bn = bt;
+          pick.split = split;
+          pick.tail = (int)rem;
+        }
       }
     }
   }
   return pick;
 }
 
-static void finalize_split(TileCfg* t, int64_t K, int* kchunk) {
+// Settle split-K: K slices of whole BK-blocks, and the number of tiles
+// computed whole first (*head; every tile when there is no split).
+static void finalize_split(TileCfg* t, int64_t K, int64_t ntiles, int* kchunk, int* head) {
+  *head = (int)std::min<int64_t>(ntiles, INT32_MAX);
   if (t->split <= 1 || K <= t->bk) {
     t->split = 1;
+    t->tail = 0;
     *kchunk = (int)std::max<int64_t>(K, 1);
     return;
   }
@@ -116,8 +145,12 @@ static void finalize_split(TileCfg* t, int64_t K, int* kchunk) {
   *kchunk = (int)chunk;
   if (t->split <= 1) {
     t->split = 1;
+    t->tail = 0;
     *kchunk = (int)K;
+    return;
   }
+  if (t->tail <= 0 || t->tail >= ntiles) t->tail = 0;  // every tile split
+  *head = t->tail ? (int)(ntiles - t->tail) : 0;
 }
 
 static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int kernel,
@@ -140,6 +173,7 @@ static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int 
   info->tile_n = t.bn;
   info->tile_k = t.bk;
   info->split_k = t.split;
+  info->split_tiles = t.split > 1 ? (t.tail ? t.tail : (int32_t)(ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn))) : 0;
   info->index_bits = index_bits;
   info->kernel = kernel;
   info->flops = 2.0 * (double)an.L * (double)an.M * (double)an.N * (double)an.K;
@@ -273,6 +307,7 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   a.tiles_n = (int32_t)ceil_div(p->an.N, p->cfg.bn);
   a.splits = p->cfg.split;
   a.kchunk = p->kchunk;
+  a.head = p->head;
   a.alpha = alpha;
   a.beta = beta;
   a.work = p->d_work;
@@ -302,6 +337,11 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   p->index_bits = p->cfg.index_bits == 64 ? 64 : index_bits_for(an);
   const int ns = split_parts(compute);
   if (ns) {
+    // the bf16 kernels split every tile or none: a tail split becomes none
+    if (p->cfg.tail) {
+      p->cfg.split = 1;
+      p->cfg.tail = 0;
+    }
     p->cfg.bk = 32;
     // bf16x3 on large problems: a 256 x 128 tile (128 x 64 per wave) halves
     // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 has three
@@ -316,8 +356,9 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
   }
   if (an.L > 1) p->cfg.split = 1;  // batch modes already multiply the tile count
-  finalize_split(&p->cfg, an.K, &p->kchunk);
-  if (ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn) * p->cfg.split * an.L >= ((int64_t)1 << 31)) {
+  const int64_t ntiles = ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn);
+  finalize_split(&p->cfg, an.K, ntiles, &p->kchunk, &p->head);
+  if (ntiles * p->cfg.split * an.L >= ((int64_t)1 << 31)) {
     delete p;
     return fail(FAMLIES_ERR_UNSUPPORTED, "the tile grid exceeds 2^31 workgroups");
   }
@@ -332,8 +373,11 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
       return st;
     }
     if (p->cfg.split > 1 && an.K > 0) {
-      const size_t es = ns ? 8 : (size_t)an.esize;
-      p->work_bytes = (size_t)p->cfg.split * (size_t)mp * (size_t)np * es;
+      // plain kernels: one BM x BN block per split tile and K slice; bf16
+      // kernels: one padded M x N plane of FP64 sums per K slice
+      p->work_bytes = ns ? (size_t)p->cfg.split * (size_t)mp * (size_t)np * 8
+                         : (size_t)p->cfg.split * (size_t)(ntiles - p->head) * (size_t)p->cfg.bm *
+                               (size_t)p->cfg.bn * (size_t)an.esize;
       hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
       if (e != hipSuccess) {
         delete p;
@@ -409,8 +453,12 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, 
   int st = analyze(dtype, compute, A, B, C, &an, &err);
   if (st != FAMLIES_OK) return fail(st, err);
   TileCfg t = choose_tiles(nullptr, an);
-  int kchunk = 0;
-  finalize_split(&t, an.K, &kchunk);
+  if (split_parts(an.compute) && t.tail) {  // as in make_plan: no split for the bf16 kernels
+    t.split = 1;
+    t.tail = 0;
+  }
+  int kchunk = 0, head = 0;
+  finalize_split(&t, an.K, ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn), &kchunk, &head);
   const int ib = index_bits_for(an);
   std::vector<int64_t> v[9];
   bool xv = false, yv = false;

@@ -25,8 +25,12 @@ struct PlainArgs {
   int32_t M, N, K, L;
   int32_t x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y (0: not packed)
   int32_t tiles_m, tiles_n, splits, kchunk;
+  // splits > 1: tiles [0, head) run whole first; tiles [head, tiles_m*tiles_n)
+  // run as `splits` K slices each, writing partial sums to `work`
+  int32_t head;
   double alpha, beta;
-  void* work;       // split-K partials [splits][tiles_m*BM][tiles_n*BN]
+  void* work;       // split-K partials [splits][tile - head][BM*BN] (plain kernels; the bf16
+                    // kernels use [splits][tiles_m*BM][tiles_n*BN] with head = 0)
 };
 
 }  // namespace famlies

@@ -71,6 +71,9 @@ struct TileCfg {
   int bm = 128, bn = 128, bk = 16;
   int split = 1;
   int index_bits = 0;  // 64: use 64-bit indexing vectors even where 32 bits reach (0: automatic)
+  // split > 1: how many tiles, the last ones in tile order, run as `split`
+  // K slices each; the others run whole K first (0: every tile is split)
+  int tail = 0;
 };
 
 void set_error(const std::string& msg);

@@ -32,13 +32,24 @@ __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_co
       (sizeof(T) == 4 && sizeof(OffT) == 4 && (XM == kRowGather || YM == kRowGather)) ? 2 : 1;
   using Tile = PlainTile<T, BM, BN, BK, XM, YM, kDepth>;
   __shared__ T smem[Tile::SMEM];
-  const int lid0 = xcd_remap(blockIdx.x, gridDim.x);
+  // Work units in launch order: without split-K, every tile of every batch
+  // plane; with split-K, first the tiles [0, head) over all of K, then each
+  // remaining tile once per K slice.  Each range is spread over the XCDs in
+  // contiguous blocks, so neighbouring tiles share an L2.
   const int ntiles = a.tiles_m * a.tiles_n;
-  const int per_batch = ntiles * a.splits;
-  const int l = lid0 / per_batch;  // batch index
-  const int lid = lid0 % per_batch;
-  const int split = lid / ntiles;
-  const int t = lid % ntiles;
+  int l = 0, split = -1, t;
+  if (a.splits == 1) {
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    l = lid / ntiles;  // batch index
+    t = lid % ntiles;
+  } else if ((int)blockIdx.x < a.head) {
+    t = xcd_remap(blockIdx.x, a.head);
+  } else {
+    const int ntail = ntiles - a.head;
+    const int v = xcd_remap(blockIdx.x - a.head, gridDim.x - a.head);
+    split = v / ntail;
+    t = a.head + v % ntail;
+  }
   const int pm = t % a.tiles_m, pn = t / a.tiles_m;  // M fastest: neighbours share Y's panel
   TileJob<OffT> j;
   // a pre-packed operand holds its batch planes back to back
@@ -59,28 +70,35 @@ __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_co
   j.N = a.N;
   j.m0 = pm * BM;
   j.n0 = pn * BN;
-  j.kbeg = split * a.kchunk;
-  j.kend = min(a.K, j.kbeg + a.kchunk);
+  j.kbeg = split < 0 ? 0 : split * a.kchunk;
+  j.kend = split < 0 ? a.K : min(a.K, j.kbeg + a.kchunk);
   j.alpha = a.alpha;
   j.beta = a.beta;
-  j.ldw = a.tiles_n * BN;
-  j.work = a.splits == 1 ? nullptr
-                         : static_cast<void*>(static_cast<T*>(a.work) +
-                                              (size_t)split * (size_t)(a.tiles_m * BM) * j.ldw);
+  // partial sums of a split tile: its own dense BM x BN block
+  j.ldw = BN;
+  j.work = split < 0 ? nullptr
+                     : static_cast<void*>(static_cast<T*>(a.work) +
+                                          ((size_t)split * (size_t)(ntiles - a.head) + (size_t)(t - a.head)) *
+                                              (size_t)(BM * BN));
   Tile::run(j, smem);
 }
 
-// C = alpha * sum_s W[s] + beta * C, the K slices summed in index order so
-// the result does not depend on scheduling.
+// For the split tiles: C = alpha * sum_s W[s] + beta * C, the K slices
+// summed in index order so the result does not depend on scheduling.  One
+// thread per element of a split tile (bm x bn blocks, row-major).
 template <typename T, typename OffT>
-__global__ __launch_bounds__(kThreads) void splitk_reduce(PlainArgs<OffT> a, int ldw, int rows) {
+__global__ __launch_bounds__(kThreads) void splitk_reduce(PlainArgs<OffT> a, int bm, int bn) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= (int64_t)a.M * a.N) return;
-  const int m = (int)(i / a.N), n = (int)(i % a.N);
+  const int ntail = a.tiles_m * a.tiles_n - a.head;
+  const int64_t per = (int64_t)bm * bn;
+  if (i >= ntail * per) return;
+  const int tt = (int)(i / per), r = (int)(i % per);
+  const int t = a.head + tt;
+  const int m = (t % a.tiles_m) * bm + r / bn, n = (t / a.tiles_m) * bn + r % bn;
+  if (m >= a.M || n >= a.N) return;
   const T* W = static_cast<const T*>(a.work);
-  const size_t plane = (size_t)rows * ldw;
   T s = T(0);
-  for (int k = 0; k < a.splits; ++k) s += W[(size_t)k * plane + (size_t)m * ldw + n];
+  for (int k = 0; k < a.splits; ++k) s += W[((size_t)k * ntail + tt) * per + r];
   T* cp = at(static_cast<T*>(a.c), (OffT)(a.cm[m] + a.cn[n]));
   const T al = static_cast<T>(a.alpha), be = static_cast<T>(a.beta);
   T v = al * s;
@@ -145,13 +163,13 @@ static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid
 template <typename T, typename OffT>
 static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L, hipStream_t s) {
   const int64_t mn = (int64_t)a.M * a.N;
-  const int eg = (int)((mn + kThreads - 1) / kThreads);
   if (L.kind == PlainLaunch::kScale) {
     hipLaunchKernelGGL((scale_c<T, OffT>), dim3((int)((mn * a.L + kThreads - 1) / kThreads)), dim3(kThreads),
                        0, s, a);
     return hipGetLastError();
   }
-  const int grid = a.tiles_m * a.tiles_n * a.splits * a.L;
+  const int64_t ntiles = (int64_t)a.tiles_m * a.tiles_n;
+  const int grid = (int)(a.splits == 1 ? ntiles * a.L : a.head + (ntiles - a.head) * a.splits);
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
   hipError_t e = hipErrorInvalidValue;
   if (L.bm == 128 && L.bn == 128 && L.bk == BK)
@@ -159,8 +177,9 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   else if (L.bm == 64 && L.bn == 64 && L.bk == BK)
     e = launch_tile<T, OffT, 64, 64, BK>(a, L.xm, L.ym, grid, s);
   if (e != hipSuccess || a.splits == 1) return e;
-  hipLaunchKernelGGL((splitk_reduce<T, OffT>), dim3(eg), dim3(kThreads), 0, s, a, a.tiles_n * L.bn,
-                     a.tiles_m * L.bm);
+  const int64_t red = (ntiles - a.head) * L.bm * L.bn;
+  hipLaunchKernelGGL((splitk_reduce<T, OffT>), dim3((int)((red + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                     a, L.bm, L.bn);
   return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ struct famlies_plan_s {
   famlies::TileCfg cfg;
   int index_bits = 32;
   int kchunk = 0;
+  int head = 0;            // split-K plans: tiles computed whole before the split ones
   void* d_off = nullptr;   // six OffT indexing vectors, then three int64 batch vectors
   size_t batch_off_bytes = 0;
   size_t off_pos[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};

@@ -49,9 +49,11 @@ void TileTable::put(const Entry& e) {
 }
 
 // Format: '#' comments; one entry per line:
-//   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits>]
-// where the optional last field 64 makes plans of that class use 64-bit
-// indexing vectors even when 32 bits reach every element.
+//   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits> [<split tiles>]]
+// where the optional index bits 64 makes plans of that class use 64-bit
+// indexing vectors even when 32 bits reach every element (0: automatic), and
+// split tiles > 0 splits only that many tiles, the last in tile order (0:
+// every tile when split > 1).
 bool TileTable::load(const std::string& path, std::string* err) {
   std::ifstream f(path);
   if (!f) {
@@ -81,6 +83,14 @@ bool TileTable::load(const std::string& path, std::string* err) {
         return false;
       }
       e.cfg.index_bits = bits == 64 ? 64 : 0;
+      int tail = 0;
+      if (is >> tail) {
+        if (tail < 0) {
+          *err = path + ":" + std::to_string(ln) + ": split tiles must be >= 0";
+          return false;
+        }
+        e.cfg.tail = tail;
+      }
     }
     e.kind = kind == "plain" ? 0 : 1;
     got.push_back(e);
@@ -95,12 +105,13 @@ bool TileTable::save(const std::string& path, std::string* err) const {
     *err = "cannot write " + path;
     return false;
   }
-  f << "# famlies tile table: kind dtype compute log2M log2N log2K bm bn bk split [index_bits]\n";
+  f << "# famlies tile table: kind dtype compute log2M log2N log2K bm bn bk split [index_bits [split_tiles]]\n";
   for (const Entry& e : entries) {
     f << (e.kind == 0 ? "plain" : "batch") << ' ' << e.dtype << ' ' << e.compute << ' ' << e.lm << ' '
       << e.ln << ' ' << e.lk << ' ' << e.cfg.bm << ' ' << e.cfg.bn << ' ' << e.cfg.bk << ' '
       << e.cfg.split;
-    if (e.cfg.index_bits) f << ' ' << e.cfg.index_bits;
+    if (e.cfg.index_bits || e.cfg.tail) f << ' ' << e.cfg.index_bits;
+    if (e.cfg.tail) f << ' ' << e.cfg.tail;
     f << '\n';
   }
   return (bool)f;

@@ -26,7 +26,7 @@ struct TileJob {
   int M, N;
   int m0, n0, kbeg, kend;
   double alpha, beta;
-  void* work;  // non-null: write partial sums here, dense [m][n] with leading dim ldw
+  void* work;  // non-null: write partial sums here, the tile's block [m - m0][n - n0] with leading dim ldw
   int ldw;
   int x_nkb, y_nkb;  // k-blocks per tile row of a pre-packed X / Y
 };
@@ -221,15 +221,16 @@ struct PlainTile {
           }
       }
     } else {
+      // partial sums into the tile's own block (tile-local rows and columns)
       T* __restrict__ W = static_cast<T*>(j.work);
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) {
-        const int n = j.n0 + wn * WTN + jj * MF::BS + r;
+        const int n = wn * WTN + jj * MF::BS + r;
 #pragma unroll
         for (int i = 0; i < MB; ++i)
 #pragma unroll
           for (int e = 0; e < MF::NACC; ++e) {
-            const int m = j.m0 + wm * WTM + i * MF::BS + MF::row(lane, e);
+            const int m = wm * WTM + i * MF::BS + MF::row(lane, e);
             *global(W + (size_t)m * j.ldw + n) = acc[i][jj][e];
           }
       }

@@ -314,3 +314,33 @@ def test_no_gpu_means_loud_failure(fm):
         pytest.skip("a GPU is present")
     with pytest.raises(fm.FamliesError):
         fm.famlies_create(0)
+
+
+def test_tail_split_choice(fm):
+    """Default tile choice (256 CUs, two workgroups each): when the tiles fill
+    whole rounds plus part of one more, only the last round's tiles are split
+    along K; a grid of exactly whole rounds is not split, and the bf16 kernels
+    (which split every tile or none) get no split."""
+    def analyze(p, dtype, compute=0, swap_c_a=False):
+        d = [fm.make_desc(t.extents, t.strides, lab) for t, lab in ((p.a, p.la), (p.b, p.lb), (p.c, p.lc))]
+        if swap_c_a:  # dA = G . B, written in A's layout
+            d = [d[2], d[1], d[0]]
+        return fm.famlies_analyze(dtype, compute, *d)[0]
+    ag = synth.autograd_case(24, 96, with_data=False)
+    info = analyze(ag, fm.FAMLIES_F32, swap_c_a=True)
+    tiles = -(-info["m"] // info["tile_m"]) * -(-info["n"] // info["tile_n"])
+    assert (info["m"], info["n"], info["k"]) in ((9216, 2304, 2304), (2304, 9216, 2304))
+    assert info["split_k"] > 1 and info["split_tiles"] == tiles % 512 and 0 < info["split_tiles"] < tiles
+    lad = synth.ladder(128, 32, with_data=False)
+    for dt in (fm.FAMLIES_F64, fm.FAMLIES_F32):
+        info = analyze(lad, dt)
+        assert info["split_k"] == 1 and info["split_tiles"] == 0  # 1024 tiles: two whole rounds
+    ring = synth.ring(48, 192, with_data=False)
+    info = analyze(ring, fm.FAMLIES_F32)
+    assert info["split_k"] > 1 and info["split_tiles"] == 72 * 72 % 512
+    for comp in (1, 2):
+        assert analyze(ring, fm.FAMLIES_F32, comp)["split_k"] == 1
+    # fewer tiles than one round: every tile split (classic split-K)
+    p16 = synth.plain16(with_data=False)
+    info = analyze(p16, fm.FAMLIES_F64)
+    assert info["split_k"] > 1 and info["split_tiles"] == (256 // info["tile_m"]) ** 2
