@@ -194,12 +194,13 @@ static int index_bits_for(const Analysis& an) {
 // sums row + col then land in [0, span) (unsigned wrap-around is exact).
 // Block strides of the block-scatter layout (Approach, "Supporting tensor
 // computations"): an operand gathered along K can be read with 16-byte loads
-// when, in every BK-block of K, its indexing vector steps by exactly one
-// element, and every run start (row offset + block start + batch offset, in
-// elements from the base pointer) is a multiple of the 16-byte vector.
+// when BK divides K (every slice whole), in every BK-block of K its indexing
+// vector steps by exactly one element, and every run start (row offset +
+// block start + batch offset, in elements from the base pointer) is a
+// multiple of the 16-byte vector.
 static bool affine_k_blocks(const std::vector<int64_t>& rows, int64_t nrows, const std::vector<int64_t>& ks,
                             int64_t K, int bk, const std::vector<int64_t>& batch, int64_t L, int64_t vk) {
-  if (K < 1) return false;
+  if (K < 1 || K % bk) return false;
   for (int64_t b = 0; b < K; b += bk) {
     const int64_t s0 = ks[(size_t)b];
     if (s0 % vk) return false;

@@ -271,8 +271,10 @@ struct PackedGather {
 // element, and every run start is 16-byte aligned, so a row's slice is a
 // contiguous run in memory.  Each thread reads VK consecutive k's of a row
 // with one 16-byte load instead of VK gathered loads and takes one offset per
-// slice; the slice that crosses kend loads element by element and
-// zero-fills.
+// slice.  Every slice is whole (the planner takes this loader only when BK
+// divides K, and split-K chunks are whole slices): a load with a fallback
+// for a partial slice made the compiler copy the other operand's freshly
+// loaded registers at the join, waiting for those loads on every step.
 template <typename T, typename OffT, int BR, int BK, int NSLOT = 1>
 struct VecKGather {
   static constexpr int VK = 16 / (int)sizeof(T);
@@ -286,9 +288,8 @@ struct VecKGather {
   typedef T vec_t __attribute__((ext_vector_type(16 / sizeof(T))));
   OffT mn[NR];
   OffT ko[NSLOT];
-  int ks[NSLOT];
   vec_t v[NSLOT][NR];
-  int r0 = 0, kk0 = 0, kend = 0;
+  int r0 = 0, kk0 = 0;
 
   __device__ __forceinline__ void init(const OffT* __restrict__ mnoff, int tile_r0, int tid) {
     kk0 = (tid % KT) * VK;
@@ -299,21 +300,11 @@ struct VecKGather {
   template <int S = 0>
   __device__ __forceinline__ void fetch_k(const OffT* __restrict__ koff, int k0) {
     ko[S] = koff[k0 + kk0];
-    ks[S] = k0;
   }
   template <int S = 0>
   __device__ __forceinline__ void load(const T* __restrict__ base) {
-    if (ks[S] + BK <= kend) {
 #pragma unroll
-      for (int i = 0; i < NR; ++i) v[S][i] = *global(reinterpret_cast<const vec_t*>(at(base, (OffT)(mn[i] + ko[S]))));
-    } else {
-      // inside a block the run continues at consecutive addresses
-#pragma unroll
-      for (int i = 0; i < NR; ++i)
-#pragma unroll
-        for (int u = 0; u < VK; ++u)
-          v[S][i][u] = ks[S] + kk0 + u < kend ? gload(base, (OffT)(mn[i] + ko[S] + u * kStep)) : T(0);
-    }
+    for (int i = 0; i < NR; ++i) v[S][i] = *global(reinterpret_cast<const vec_t*>(at(base, (OffT)(mn[i] + ko[S]))));
   }
   template <int S = 0>
   __device__ __forceinline__ void store(T* __restrict__ lds, int /*k0*/, int /*kend*/) const {

@@ -116,14 +116,14 @@ __device__ __forceinline__ void store_split4(float x0, float x1, float x2, float
 }
 
 // K-gathered from affine unit-stride K blocks: 16-byte loads of four k's
-// (the loads zero-fill past kend).
+// (every slice whole: the planner takes this loader only when BK divides K).
 template <typename OffT, int BR, int NS>
 struct SplitLoader<OffT, BR, NS, kVecK> {
   using G = VecKGather<float, OffT, BR, kB3K>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
-  __device__ __forceinline__ void set_kend(int kend) { g.kend = kend; }
+  __device__ __forceinline__ void set_kend(int) {}
   __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
   __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {

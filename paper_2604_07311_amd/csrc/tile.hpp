@@ -85,8 +85,6 @@ struct PlainTile {
     gy.init(j.ymn, j.n0, tid);
     if constexpr (XM == kPacked) gx.nkb = j.x_nkb;
     if constexpr (YM == kPacked) gy.nkb = j.y_nkb;
-    if constexpr (XM == kVecK) gx.kend = j.kend;
-    if constexpr (YM == kVecK) gy.kend = j.kend;
 
     typename MF::Acc acc[MB][NB];
 #pragma unroll

@@ -193,24 +193,31 @@ def test_cost_model_orders_rows_by_the_gathered_operand(fm, oracle_lib):
     np.testing.assert_array_equal(out, want)
 
 
-def _mk(labels, ext, orders):
-    lays = [synth.layout([ext[ch] for ch in lab], order=o) for lab, o in zip(labels, orders)]
+def _mk(labels, ext, orders, pads=(None, None, None)):
+    lays = [synth.layout([ext[ch] for ch in lab], order=o, pad=pd) for lab, o, pd in zip(labels, orders, pads)]
     return synth.Problem("affine", *labels, *lays, 1.0, 0.5)
 
 
 def test_affine_block_flags(fm):
     """Block strides: the plan reads an operand with 16-byte loads (kernel id
-    +16 for X, +32 for Y) exactly when it is K-gathered, each K-slice of its
-    indexing vector steps by one element, and every run start is a multiple
-    of the 16-byte vector (2 FP64 or 4 FP32 elements)."""
+    +16 for X, +32 for Y) exactly when it is K-gathered, the K slice (16 FP64
+    / 32 FP32 elements) divides K, each K-slice of its indexing vector steps
+    by one element, and every run start is a multiple of the 16-byte vector
+    (2 FP64 or 4 FP32 elements)."""
     F64, F32 = fm.FAMLIES_F64, fm.FAMLIES_F32
     lad = synth.ladder(32, 4, seed=1)           # W stored (e,a,f,b): K blocks inside e
     for dt in (F64, F32):
         info, _ = analyze(fm, lad, dt)
         assert info["kernel"] == 1 + 16 + 32
+    # rows 34 elements apart (k extent 32, 2 padding): 34 % 2 == 0, 34 % 4 != 0
+    rows34 = _mk(("ki", "kj", "ji"), {"k": 32, "i": 20, "j": 6}, (None, None, None), ([2, 0], [2, 0], None))
+    assert analyze(fm, rows34, F64)[0]["kernel"] == 49
+    assert analyze(fm, rows34, F32)[0]["kernel"] == 1
+    # K = 30: unit stride and aligned rows (30 % 2 == 0), but the last slice
+    # would be partial, so both operands are gathered element by element
     rows30 = _mk(("ki", "kj", "ji"), {"k": 30, "i": 20, "j": 6}, (None, None, None))
-    assert analyze(fm, rows30, F64)[0]["kernel"] == 49      # 30 % 2 == 0
-    assert analyze(fm, rows30, F32)[0]["kernel"] == 1       # 30 % 4 != 0
+    assert analyze(fm, rows30, F64)[0]["kernel"] == 1
+    assert analyze(fm, rows30, F32)[0]["kernel"] == 1
     # K modes that do not fuse and a K extent that splits the 32-wide slices
     split = _mk(("kil", "klj", "ij"), {"k": 40, "l": 3, "i": 20, "j": 8}, ([0, 1, 2], [0, 2, 1], [0, 1]))
     info, _ = analyze(fm, split, F32)

@@ -82,14 +82,17 @@ def _check(gpu, p, dtype, K, expect_kernel_bits, tmp_path=None, bm=None):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bm", [None, 128])
 def test_fused_k_ragged(gpu, tmp_path, dtype, bm):
-    """A[k,l,i] B[k,l,j] -> C[j,i]: K = 40*13 = 520 fuses to one unit-stride
-    mode, not a multiple of the K slice (planned tiles, then forced 128 x 128)."""
-    ext = {"k": 40, "l": 13, "i": 600, "j": 520}
+    """A[k,l,i] B[k,l,j] -> C[j,i]: K = 40*16 = 640 fuses to one unit-stride
+    mode, a multiple of the K slice; then K = 40*13 = 520, which is not, and
+    both operands are gathered (planned tiles, then forced 128 x 128)."""
+    ext = {"k": 40, "l": 16, "i": 600, "j": 520}
     p = _problem("kli", "klj", "ji", ext, (None, None, None), seed=201)
-    got = _check(gpu, p, dtype, 520, 48, tmp_path, bm)
+    got = _check(gpu, p, dtype, 640, 48, tmp_path, bm)
+    ext13 = dict(ext, l=13)
+    _check(gpu, _problem("kli", "klj", "ji", ext13, (None, None, None), seed=205), dtype, 520, 0, tmp_path, bm)
     # unaligned base pointers: same plan shape, gathering path, same values up to rounding
     q = _shift(p)
-    got_q = _check(gpu, q, dtype, 520, 48, tmp_path, bm)
+    got_q = _check(gpu, q, dtype, 640, 48, tmp_path, bm)
     np.testing.assert_allclose(got_q[1:], got, rtol=0, atol=1e-12 if dtype == "f64" else 1e-4)
 
 
@@ -112,9 +115,13 @@ def test_batch_modes(gpu, dtype):
 
 
 def test_row_offsets_decide(gpu):
-    """Rows of A and B 30 elements apart: 16-byte runs for FP64 (2 elements)
-    but not for FP32 (4 elements), where both are gathered."""
-    ext = {"k": 30, "i": 200, "j": 64}
-    p = _problem("ki", "kj", "ji", ext, (None, None, None), seed=204)
-    _check(gpu, p, "f64", 30, 48)
-    _check(gpu, p, "f32", 30, 0)
+    """Rows of A and B 34 elements apart (k extent 32 plus 2 padding): 16-byte
+    runs for FP64 (2 elements) but not for FP32 (4 elements), where both are
+    gathered."""
+    ext = {"k": 32, "i": 200, "j": 64}
+    lays = [synth.layout([ext[ch] for ch in lab], pad=pd) for lab, pd in (("ki", [2, 0]), ("kj", [2, 0]), ("ji", None))]
+    p = synth.Problem("affine_rows34", "ki", "kj", "ji", *lays, 1.0, 0.5)
+    rng = np.random.default_rng(204)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
+    _check(gpu, p, "f64", 32, 48)
+    _check(gpu, p, "f32", 32, 0)

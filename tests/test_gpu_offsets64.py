@@ -86,8 +86,8 @@ def test_random_general_labels_64bit(gpu, tmp_path, seed):
 
 
 def test_bf16x3_64bit(gpu, tmp_path):
-    p = round_inputs(synth.ladder(20, 6, seed=320, dist="outliers"), "f32")
-    K = 400
+    p = round_inputs(synth.ladder(24, 6, seed=320, dist="outliers"), "f32")
+    K = 576
     exact, d = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:], want_cond=True)
     _, dp = oracle.contract(p.alpha, *p.oracle_args()[:4], 0.0, *p.oracle_args()[4:], want_cond=True)
     got, info = _run64(gpu, tmp_path, p, "f32", compute="bf16x3")
