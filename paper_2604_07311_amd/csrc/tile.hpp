@@ -130,21 +130,23 @@ struct PlainTile {
       }
     } else if (nk > 0) {
       // DEPTH 2: slice s lives in register slot s % 2 and LDS buffer s % 2;
-      // data two slices ahead, offsets three ahead.
+      // data two slices ahead, offsets three ahead.  Loads and offset
+      // fetches are issued on every step, past the last slice too (their
+      // slice index clamped to the last one, their data never stored): with
+      // the same loads on every path the compiler's wait before a store
+      // counts only the slice being stored, not the loads just issued.
+      const int klast = j.kbeg + (nk - 1) * BK;
+      auto kc = [&](int k0) { return k0 < klast ? k0 : klast; };
       gx.template fetch_k<0>(j.xk, j.kbeg);
       gy.template fetch_k<0>(j.yk, j.kbeg);
       gx.template load<0>(X);
       gy.template load<0>(Y);
-      if (nk > 1) {
-        gx.template fetch_k<1>(j.xk, j.kbeg + BK);
-        gy.template fetch_k<1>(j.yk, j.kbeg + BK);
-        gx.template load<1>(X);
-        gy.template load<1>(Y);
-      }
-      if (nk > 2) {
-        gx.template fetch_k<0>(j.xk, j.kbeg + 2 * BK);
-        gy.template fetch_k<0>(j.yk, j.kbeg + 2 * BK);
-      }
+      gx.template fetch_k<1>(j.xk, kc(j.kbeg + BK));
+      gy.template fetch_k<1>(j.yk, kc(j.kbeg + BK));
+      gx.template load<1>(X);
+      gy.template load<1>(Y);
+      gx.template fetch_k<0>(j.xk, kc(j.kbeg + 2 * BK));
+      gy.template fetch_k<0>(j.yk, kc(j.kbeg + 2 * BK));
       gx.template store<0>(smem, j.kbeg, j.kend);
       gy.template store<0>(smem + XS, j.kbeg, j.kend);
       __syncthreads();
@@ -152,14 +154,10 @@ struct PlainTile {
       // and holds the offsets of slice it + 2; slot S^1 holds slice it + 1.
       auto step = [&](auto sc, int it) {
         constexpr int S = decltype(sc)::value;
-        if (it + 2 < nk) {
-          gx.template load<S>(X);
-          gy.template load<S>(Y);
-        }
-        if (it + 3 < nk) {
-          gx.template fetch_k<S ^ 1>(j.xk, j.kbeg + (it + 3) * BK);
-          gy.template fetch_k<S ^ 1>(j.yk, j.kbeg + (it + 3) * BK);
-        }
+        gx.template load<S>(X);
+        gy.template load<S>(Y);
+        gx.template fetch_k<S ^ 1>(j.xk, kc(j.kbeg + (it + 3) * BK));
+        gy.template fetch_k<S ^ 1>(j.yk, kc(j.kbeg + (it + 3) * BK));
         multiply(smem + S * (XS + YS), wm, wn, g, r, acc);
         if (it + 1 < nk) {
           T* nx = smem + (S ^ 1) * (XS + YS);
