@@ -22,14 +22,19 @@ namespace famlies {
 
 template <typename T, typename OffT, int BM, int BN, int BK, int XM, int YM>
 __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_contract(PlainArgs<OffT> a) {
-  // A row-gathered operand issues one load per element along K, so its slice
-  // takes longer to arrive: FP32 tiles with 32-bit offsets then keep two
-  // slices in flight (measured: ring FP32, Y row-gathered, 69.8 % -> 75.7 %
-  // of peak; with both operands K-gathered the deeper pipeline lost 8 %).
-  // FP64 tiles need every register for the accumulators, and 64-bit offsets
-  // double the registers of the indexing vectors.
+  // Two slices in flight where the registers allow it: FP32 tiles with a
+  // row-gathered operand and 32-bit offsets (one load per element along K,
+  // so its slice takes longest to arrive), and tiles whose operands are both
+  // read in affine 16-byte blocks (few registers per slice; FP64 only with
+  // 32-bit offsets).  Measured on the ladder (both affine): FP64 82 -> 87 %,
+  // FP32 83 -> 88 %, FP32 with 64-bit offsets 77 -> 85 % of peak.  Other
+  // FP64 tiles would spill (the accumulators take half the registers); with
+  // both operands element-gathered along K the deeper pipeline was no faster.
   static constexpr int kDepth =
-      (sizeof(T) == 4 && sizeof(OffT) == 4 && (XM == kRowGather || YM == kRowGather)) ? 2 : 1;
+      ((sizeof(OffT) == 4 && sizeof(T) == 4 && (XM == kRowGather || YM == kRowGather)) ||
+       ((sizeof(OffT) == 4 || sizeof(T) == 4) && XM == kVecK && YM == kVecK))
+          ? 2
+          : 1;
   using Tile = PlainTile<T, BM, BN, BK, XM, YM, kDepth>;
   __shared__ T smem[Tile::SMEM];
   // Work units in launch order: without split-K, every tile of every batch
