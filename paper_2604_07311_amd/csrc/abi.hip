@@ -346,8 +346,11 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     p->cfg.bk = 32;
     // bf16x3 on large problems: a 256 x 128 tile (128 x 64 per wave) halves
     // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 has three
-    // accumulators per block and stays at 128 x 128)
-    if (!force && ns == 2 && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1) {
+    // accumulators per block and stays at 128 x 128).  It has registers for
+    // one slice in flight only, so it is taken when both operands are read
+    // along K; a row-gathered operand keeps the 128 x 128 tile with two
+    // slices in flight (ring o=48 v=192: 186 -> 201 TFLOP/s FP32-equivalent).
+    if (!force && ns == 2 && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1 && an.x_kfast && an.y_kfast) {
       p->cfg.bm = 256;
       p->cfg.bn = 128;
     }

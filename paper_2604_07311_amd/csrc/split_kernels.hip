@@ -47,14 +47,14 @@ constexpr int kB3LD = kB3K + 8;     // row pitch in bf16
 // tiles + t * tile_elems).  K-gathered threads own pairs of consecutive k's
 // (one packed dword per row and part); row-gathered threads own a run of k's
 // in one row (8-byte stores).  EDGE: the slice reaches past kend.
-template <int NS, typename G, bool KFAST, bool EDGE>
+template <int NS, typename G, bool KFAST, bool EDGE, int S>
 __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile_elems, int k0, int kend) {
   if constexpr (KFAST) {
     static_assert(G::KVT == 2, "K-gathered bf16 split stores pairs of k");
 #pragma unroll
     for (int i = 0; i < G::E / 2; ++i) {
       uint32_t p[NS];
-      split2<NS>(gg.template val<EDGE>(2 * i, k0, kend), gg.template val<EDGE>(2 * i + 1, k0, kend), p);
+      split2<NS>(gg.template val<EDGE, S>(2 * i, k0, kend), gg.template val<EDGE, S>(2 * i + 1, k0, kend), p);
       const int idx = gg.lds_index(2 * i, kB3LD);
 #pragma unroll
       for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
@@ -64,8 +64,8 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
 #pragma unroll
     for (int q = 0; q < G::E / 4; ++q) {
       uint32_t p0[NS], p1[NS];
-      split2<NS>(gg.template val<EDGE>(4 * q, k0, kend), gg.template val<EDGE>(4 * q + 1, k0, kend), p0);
-      split2<NS>(gg.template val<EDGE>(4 * q + 2, k0, kend), gg.template val<EDGE>(4 * q + 3, k0, kend), p1);
+      split2<NS>(gg.template val<EDGE, S>(4 * q, k0, kend), gg.template val<EDGE, S>(4 * q + 1, k0, kend), p0);
+      split2<NS>(gg.template val<EDGE, S>(4 * q + 2, k0, kend), gg.template val<EDGE, S>(4 * q + 3, k0, kend), p1);
       const int idx = gg.lds_index(4 * q, kB3LD);
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
@@ -79,23 +79,26 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
 // Operand loader of the split kernels: a gathered FP32 slice split at the
 // LDS store (modes kRowGather, kKGather), or pre-packed bf16 parts copied as
 // they are (kPacked: block (tile, kb) holds the NS part planes of BR x BK
-// bf16, [row][k], zero-filled past the edges; see famlies_pack).
-template <typename OffT, int BR, int NS, int MODE>
+// bf16, [row][k], zero-filled past the edges; see famlies_pack).  NSLOT
+// slices in flight; each phase takes its slot as a template argument.
+template <typename OffT, int BR, int NS, int MODE, int NSLOT = 1>
 struct SplitLoader {
   static_assert(MODE == kRowGather || MODE == kKGather, "every other mode has its own loader");
   static constexpr bool KF = MODE == kKGather;
-  using G = TileGather<float, OffT, BR, kB3K, KF, KF ? 2 : 1>;
+  using G = TileGather<float, OffT, BR, kB3K, KF, KF ? 2 : 1, NSLOT>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
-  __device__ __forceinline__ void set_kend(int) {}
-  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
-  __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
+  template <int S = 0>
+  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.template fetch_k<S>(koff, k0); }
+  template <int S = 0>
+  __device__ __forceinline__ void load(const void* base) { g.template load<S>(static_cast<const float*>(base)); }
+  template <int S = 0>
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int k0, int kend) const {
     if (k0 + kB3K <= kend)
-      store_split<NS, G, KF, false>(g, tiles, tile_elems, k0, kend);
+      store_split<NS, G, KF, false, S>(g, tiles, tile_elems, k0, kend);
     else
-      store_split<NS, G, KF, true>(g, tiles, tile_elems, k0, kend);
+      store_split<NS, G, KF, true, S>(g, tiles, tile_elems, k0, kend);
   }
 };
 
@@ -117,62 +120,75 @@ __device__ __forceinline__ void store_split4(float x0, float x1, float x2, float
 
 // K-gathered from affine unit-stride K blocks: 16-byte loads of four k's
 // (every slice whole: the planner takes this loader only when BK divides K).
-template <typename OffT, int BR, int NS>
-struct SplitLoader<OffT, BR, NS, kVecK> {
-  using G = VecKGather<float, OffT, BR, kB3K>;
+template <typename OffT, int BR, int NS, int NSLOT>
+struct SplitLoader<OffT, BR, NS, kVecK, NSLOT> {
+  using G = VecKGather<float, OffT, BR, kB3K, NSLOT>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
-  __device__ __forceinline__ void set_kend(int) {}
-  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.fetch_k(koff, k0); }
-  __device__ __forceinline__ void load(const void* base) { g.load(static_cast<const float*>(base)); }
+  template <int S = 0>
+  __device__ __forceinline__ void fetch_k(const OffT* koff, int k0) { g.template fetch_k<S>(koff, k0); }
+  template <int S = 0>
+  __device__ __forceinline__ void load(const void* base) { g.template load<S>(static_cast<const float*>(base)); }
+  template <int S = 0>
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {
 #pragma unroll
     for (int i = 0; i < G::NR; ++i) {
-      const auto v = g.v[0][i];
+      const auto v = g.v[S][i];
       store_split4<NS>(v[0], v[1], v[2], v[3], tiles, tile_elems, (g.r0 + i * G::RSTEP) * kB3LD + g.kk0);
     }
   }
 };
 
-template <typename OffT, int BR, int NS>
-struct SplitLoader<OffT, BR, NS, kPacked> {
+template <typename OffT, int BR, int NS, int NSLOT>
+struct SplitLoader<OffT, BR, NS, kPacked, NSLOT> {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   static constexpr int VPT = BR * kB3K / 8 / kThreads;  // 16-byte vectors per thread and part
   static_assert(VPT >= 1, "packed block does not divide the workgroup");
-  u32x4 v[NS][VPT];
-  int tile = 0, kb = 0, nkb = 1, tid = 0;
+  u32x4 v[NSLOT][NS][VPT];
+  int tile = 0, kb[NSLOT] = {}, nkb = 1, tid = 0;
   __device__ __forceinline__ void init(const OffT*, int tile_r0, int t) {
     tile = tile_r0 / BR;
     tid = t;
   }
-  __device__ __forceinline__ void set_kend(int) {}
-  __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb = k0 / kB3K; }
+  template <int S = 0>
+  __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb[S] = k0 / kB3K; }
+  template <int S = 0>
   __device__ __forceinline__ void load(const void* base) {
-    const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb) * (size_t)(NS * BR * kB3K);
+    const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb[S]) * (size_t)(NS * BR * kB3K);
 #pragma unroll
     for (int t = 0; t < NS; ++t)
 #pragma unroll
-      for (int q = 0; q < VPT; ++q) v[t][q] = reinterpret_cast<const u32x4*>(blk + t * BR * kB3K)[tid + q * kThreads];
+      for (int q = 0; q < VPT; ++q) v[S][t][q] = reinterpret_cast<const u32x4*>(blk + t * BR * kB3K)[tid + q * kThreads];
   }
+  template <int S = 0>
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {
 #pragma unroll
     for (int t = 0; t < NS; ++t)
 #pragma unroll
       for (int q = 0; q < VPT; ++q) {
         const int e = (tid + q * kThreads) * 8;
-        *reinterpret_cast<u32x4*>(tiles + t * tile_elems + (e / kB3K) * kB3LD + e % kB3K) = v[t][q];
+        *reinterpret_cast<u32x4*>(tiles + t * tile_elems + (e / kB3K) * kB3LD + e % kB3K) = v[S][t][q];
       }
   }
 };
 
 // One workgroup: a BM x BN tile of C, 2 x 2 waves of (BM/2) x (BN/2), each
 // made of 32 x 32 MFMA blocks.
+// Two slices in flight except for the 256-row tile, whose two accumulator
+// sets fill the accumulation registers and whose loads would then spill.
+template <typename OffT, int BM, int NS, int XM, int YM>
+constexpr int kSplitDepth = BM == 256 ? 1 : 2;
+
 template <typename OffT, int BM, int BN, int XM, int YM, int NS>
 __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   constexpr int BK = kB3K;
-  using GX = SplitLoader<OffT, BM, NS, XM>;
-  using GY = SplitLoader<OffT, BN, NS, YM>;
+  // Slices in flight: one workgroup per CU holds the accumulators, so the
+  // next slice's loads must hide behind a single slice of bf16 MFMAs; two
+  // slices in flight where the registers allow it.
+  constexpr int DEPTH = kSplitDepth<OffT, BM, NS, XM, YM>;
+  using GX = SplitLoader<OffT, BM, NS, XM, DEPTH>;
+  using GY = SplitLoader<OffT, BN, NS, YM, DEPTH>;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
   constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per part tile
@@ -208,8 +224,6 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
   gy.init(a.ymn, n0, tid);
   gx.nkb = a.x_nkb;
   gy.nkb = a.y_nkb;
-  gx.set_kend(kend);
-  gy.set_kend(kend);
 
   f32x16 acc[NS][MB][NB];  // acc[o]: products whose parts' orders sum to o
 #pragma unroll
@@ -220,60 +234,100 @@ __global__ __launch_bounds__(kThreads) void split_contract(PlainArgs<OffT> a) {
       for (int j = 0; j < NB; ++j) acc[o][i][j] = f32x16{};
 
   const int g = lane / 32, r = lane % 32;
-  auto stage_store = [&](int buf, int k0) {
+  auto stage_store = [&](auto sc, int buf, int k0) {
+    constexpr int S = decltype(sc)::value;
     __bf16* base = smem + buf * STAGE;
-    gx.store(base, XS, k0, kend);
-    gy.store(base + NS * XS, YS, k0, kend);
+    gx.template store<S>(base, XS, k0, kend);
+    gy.template store<S>(base + NS * XS, YS, k0, kend);
   };
-  if (nk > 0) {
-    gx.fetch_k(a.xk, kbeg);
-    gy.fetch_k(a.yk, kbeg);
-    gx.load(X);
-    gy.load(Y);
-    if (nk > 1) {
-      gx.fetch_k(a.xk, kbeg + BK);
-      gy.fetch_k(a.yk, kbeg + BK);
-    }
-    stage_store(0, kbeg);
-    __syncthreads();
-    for (int it = 0; it < nk; ++it) {
-      const int cur = it & 1;
-      const bool more = it + 1 < nk;
-      if (more) {
-        gx.load(X);
-        gy.load(Y);
-        if (it + 2 < nk) {
-          gx.fetch_k(a.xk, kbeg + (it + 2) * BK);
-          gy.fetch_k(a.yk, kbeg + (it + 2) * BK);
-        }
-      }
-      const __bf16* xs = smem + cur * STAGE;
-      const __bf16* ys = xs + NS * XS;
-      // lane group g covers k in [16g, 16g + 16) of the slice, in two steps of 8
+  auto multiply = [&](int cur) {
+    const __bf16* xs = smem + cur * STAGE;
+    const __bf16* ys = xs + NS * XS;
+    // lane group g covers k in [16g, 16g + 16) of the slice, in two steps of 8
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        bf16x8 av[NS][MB], bv[NS][NB];
+    for (int s = 0; s < 2; ++s) {
+      bf16x8 av[NS][MB], bv[NS][NB];
 #pragma unroll
-        for (int p = 0; p < NS; ++p) {
-#pragma unroll
-          for (int i = 0; i < MB; ++i)
-            av[p][i] = *reinterpret_cast<const bf16x8*>(xs + p * XS + (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8);
-#pragma unroll
-          for (int j = 0; j < NB; ++j)
-            bv[p][j] = *reinterpret_cast<const bf16x8*>(ys + p * YS + (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8);
-        }
+      for (int p = 0; p < NS; ++p) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
+          av[p][i] = *reinterpret_cast<const bf16x8*>(xs + p * XS + (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8);
 #pragma unroll
-          for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int pa = 0; pa < NS; ++pa)
-#pragma unroll
-              for (int pb = 0; pa + pb < NS; ++pb)
-                acc[pa + pb][i][j] = mma_bf16(av[pa][i], bv[pb][j], acc[pa + pb][i][j]);
+        for (int j = 0; j < NB; ++j)
+          bv[p][j] = *reinterpret_cast<const bf16x8*>(ys + p * YS + (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8);
       }
-      if (more) stage_store(cur ^ 1, kbeg + (it + 1) * BK);
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int pa = 0; pa < NS; ++pa)
+#pragma unroll
+            for (int pb = 0; pa + pb < NS; ++pb)
+              acc[pa + pb][i][j] = mma_bf16(av[pa][i], bv[pb][j], acc[pa + pb][i][j]);
+    }
+  };
+  constexpr auto slot0 = std::integral_constant<int, 0>{};
+  if (nk > 0) {
+    if constexpr (DEPTH == 1) {
+      gx.fetch_k(a.xk, kbeg);
+      gy.fetch_k(a.yk, kbeg);
+      gx.load(X);
+      gy.load(Y);
+      if (nk > 1) {
+        gx.fetch_k(a.xk, kbeg + BK);
+        gy.fetch_k(a.yk, kbeg + BK);
+      }
+      stage_store(slot0, 0, kbeg);
       __syncthreads();
+      for (int it = 0; it < nk; ++it) {
+        const int cur = it & 1;
+        const bool more = it + 1 < nk;
+        if (more) {
+          gx.load(X);
+          gy.load(Y);
+          if (it + 2 < nk) {
+            gx.fetch_k(a.xk, kbeg + (it + 2) * BK);
+            gy.fetch_k(a.yk, kbeg + (it + 2) * BK);
+          }
+        }
+        multiply(cur);
+        if (more) stage_store(slot0, cur ^ 1, kbeg + (it + 1) * BK);
+        __syncthreads();
+      }
+    } else {
+      // Slice s in register slot s % 2 and LDS stage s % 2; data two slices
+      // ahead, offsets three ahead.  The loads are issued on every step, past
+      // the last slice too (slice index clamped, data never stored), so the
+      // wait before a store covers only the slice being stored.
+      const int klast = kbeg + (nk - 1) * BK;
+      auto kc = [&](int k0) { return k0 < klast ? k0 : klast; };
+      gx.template fetch_k<0>(a.xk, kbeg);
+      gy.template fetch_k<0>(a.yk, kbeg);
+      gx.template load<0>(X);
+      gy.template load<0>(Y);
+      gx.template fetch_k<1>(a.xk, kc(kbeg + BK));
+      gy.template fetch_k<1>(a.yk, kc(kbeg + BK));
+      gx.template load<1>(X);
+      gy.template load<1>(Y);
+      gx.template fetch_k<0>(a.xk, kc(kbeg + 2 * BK));
+      gy.template fetch_k<0>(a.yk, kc(kbeg + 2 * BK));
+      stage_store(slot0, 0, kbeg);
+      __syncthreads();
+      auto step = [&](auto sc, int it) {
+        constexpr int S = decltype(sc)::value;
+        gx.template load<S>(X);
+        gy.template load<S>(Y);
+        gx.template fetch_k<S ^ 1>(a.xk, kc(kbeg + (it + 3) * BK));
+        gy.template fetch_k<S ^ 1>(a.yk, kc(kbeg + (it + 3) * BK));
+        multiply(S);
+        if (it + 1 < nk) stage_store(std::integral_constant<int, S ^ 1>{}, S ^ 1, kbeg + (it + 1) * BK);
+        __syncthreads();
+      };
+      for (int it = 0; it < nk; it += 2) {
+        step(std::integral_constant<int, 0>{}, it);
+        if (it + 1 < nk) step(std::integral_constant<int, 1>{}, it + 1);
+      }
     }
   }
 
