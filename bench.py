@@ -261,12 +261,12 @@ def cpu_baseline(p, target_s=12.0):
 # traffic is reported as null until the counters are taken again.
 TRAFFIC = {
     # plain_contract<double,u32,128,128,16,3,3>, ladder v=128 o=32
-    ("ladder", "f64", 128, 32): {"fetch_kib": 2.9616e6, "write_kib": 131072.0, "fetch_scale": 1.9999,
-                                 "write_scale": 1.0, "sources": "6a20874ded5d64f5",
+    ("ladder", "f64", 128, 32): {"fetch_kib": 3.5734e6, "write_kib": 131072.0, "fetch_scale": 1.9999,
+                                 "write_scale": 1.0, "sources": "ac916bcda261ace3",
                                  "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, profiles/plain_contract_ladder_v128_o32_write_size.md"},
     # plain_contract<float,u32,128,128,32,3,3>, ladder v=128 o=32
-    ("ladder", "f32", 128, 32): {"fetch_kib": 1.1404e6, "write_kib": 65536.0, "fetch_scale": 1.9999,
-                                 "write_scale": 1.0, "sources": "6a20874ded5d64f5",
+    ("ladder", "f32", 128, 32): {"fetch_kib": 2.7993e6, "write_kib": 65536.0, "fetch_scale": 1.9999,
+                                 "write_scale": 1.0, "sources": "ac916bcda261ace3",
                                  "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, profiles/plain_contract_ladder_v128_o32_write_size.md"},
 }
 
