@@ -5,11 +5,14 @@
 // (labels, grouping, orientation, indexing vectors), then cuts all problems
 // into (problem, tile) work items and deals them to a fixed grid of
 // workgroups: problems are spread over the XCDs by estimated cost (so a
-// problem's tiles share one L2), and inside an XCD items go, largest first,
-// to the least-loaded workgroup (longest-processing-time-first), so a
-// problem's tiles run side by side on different workgroups.  The device
-// work list is static, so a launch needs no counters, no atomics and no
-// clearing, and can be captured in a HIP graph and replayed.  This is the
+// problem's tiles share one L2), and each XCD's items form one queue,
+// largest problems first with a problem's tiles consecutive.  The
+// workgroups of an XCD take items from its queue with an atomic counter, so
+// a problem's tiles run side by side and no workgroup idles while its queue
+// has work (longest-processing-time-first, decided as the launch runs).  The
+// last workgroup of a queue to finish sets its counters back to zero, so a
+// launch needs no clearing and can be captured in a HIP graph and replayed;
+// launches of one batched plan must not overlap.  This is the
 // on-GPU counterpart of running many tile-sized contractions (Approach,
 // "Supporting tensor computations": tiling of tensors, tensor-of-tensors
 // and dynamic blocking) and of block-size selection per problem (the
@@ -21,7 +24,6 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
-#include <queue>
 #include <string>
 #include <vector>
 
@@ -47,7 +49,9 @@ struct BatchItem {
 struct BatchArgs {
   const BatchProblemDev* probs;
   const BatchItem* items;
-  const int32_t* wg_start;  // items of workgroup w: [wg_start[w], wg_start[w+1])
+  const int32_t* q_start;  // items of queue q: [q_start[q], q_start[q+1]) (kXcds queues)
+  int32_t* counters;       // [q]: next item of queue q; [kXcds + q]: workgroups done with it
+  int32_t per_queue;       // workgroups serving each queue (workgroup w serves w % kXcds)
   const uint32_t* pool;     // indexing vectors: byte offsets from each operand's lowest element
   const void* const* A;
   const void* const* B;
@@ -70,10 +74,15 @@ __global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
   constexpr int SM = PlainTile<T, 128, 128, BK, true, true>::SMEM;
   __shared__ T smem[SM];
-  const int w = blockIdx.x;
-  const int beg = a.wg_start[w], end = a.wg_start[w + 1];
-  for (int it = beg; it < end; ++it) {
-    const BatchItem item = a.items[it];
+  __shared__ int next;
+  const int q = (int)blockIdx.x % kXcds;
+  const int beg = a.q_start[q], count = a.q_start[q + 1] - beg;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(a.counters + q, 1);
+    __syncthreads();
+    const int it = next;
+    if (it >= count) break;  // the counter only grows: every workgroup gets here
+    const BatchItem item = a.items[beg + it];
     const BatchProblemDev& P = a.probs[item.prob];
     const int flags = P.flags;
     const bool swapped = flags & 1;
@@ -113,13 +122,19 @@ __global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
     }
     __syncthreads();
   }
+  // every workgroup of the queue has drawn past its end: the last one to
+  // arrive clears the queue's counters for the next launch
+  if (threadIdx.x == 0 && atomicAdd(a.counters + kXcds + q, 1) == a.per_queue - 1) {
+    a.counters[q] = 0;
+    a.counters[kXcds + q] = 0;
+  }
 }
 
 struct BatchPlan {
   int dtype = FAMLIES_F32;
   int64_t n = 0;
   int grid = 0;
-  void* d_buf = nullptr;  // probs | items | wg_start | pool, one allocation
+  void* d_buf = nullptr;  // probs | items | queues | scale list | pool, one allocation
   BatchArgs args{};
   int64_t n_items = 0;
   double flops = 0.0;
@@ -251,8 +266,9 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     delete bp;
     return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: indexing vectors exceed 2^31 entries");
   }
-  // Grid: as many workgroups as can be resident at once (every one of them
-  // runs its whole item list, so none may wait for another to finish).
+  // Grid: as many workgroups as can be resident at once, a multiple of the
+  // XCD count (workgroup w serves queue w % 8).  No workgroup waits for
+  // another: one that starts late finds its queue drained and leaves.
   int per_cu = 0;
   {
     DeviceGuard dg0(h->device);
@@ -261,57 +277,41 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_contract<float>, kThreads, 0);
     if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   }
-  const int grid = std::max(8, (per_cu * h->num_cus) / 8 * 8);
-  const int per_xcd = grid / 8;
+  const int grid = std::max(kXcds, (per_cu * h->num_cus) / kXcds * kXcds);
   // 1) problems -> XCDs, largest first, to the least-loaded XCD
   std::vector<int64_t> order((size_t)n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t b) { return prob_cost[(size_t)a] > prob_cost[(size_t)b]; });
-  std::vector<double> xload(8, 0.0);
-  std::vector<std::vector<Job>> xjobs(8);
+  std::vector<double> xload(kXcds, 0.0);
+  std::vector<std::vector<Job>> xjobs(kXcds);
   for (int64_t p : order) {
     if (per_prob[(size_t)p].empty()) continue;
     int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
     xload[(size_t)x] += prob_cost[(size_t)p];
     for (const Job& jb : per_prob[(size_t)p]) xjobs[(size_t)x].push_back(jb);
   }
-  // 2) inside an XCD: items, largest first, to its least-loaded workgroup
-  //    (workgroup w runs on XCD w % 8).  A problem's tiles are consecutive in
-  //    this order, so they go to different workgroups at about the same
-  //    estimated time and run side by side: their shared operand panels are
-  //    then read once into the XCD's L2 instead of once per tile.  Each
-  //    workgroup keeps its items in start-time order for the same reason.
-  std::vector<std::vector<Job>> wjobs((size_t)grid);
-  for (int x = 0; x < 8; ++x) {
+  // 2) each XCD's queue: largest problems first, a problem's tiles
+  //    consecutive, so the workgroups that draw them run them side by side
+  //    and the problem's operand panels are read once into the XCD's L2
+  std::vector<BatchItem> items;
+  std::vector<int32_t> q_start(kXcds + 1, 0);
+  for (int x = 0; x < kXcds; ++x) {
+    q_start[(size_t)x] = (int32_t)items.size();
     auto& js = xjobs[(size_t)x];
     std::stable_sort(js.begin(), js.end(), [](const Job& a, const Job& b) {
       return a.cost != b.cost ? a.cost > b.cost : a.prob < b.prob;
     });
-    typedef std::pair<double, int> Slot;
-    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
-    for (int k = 0; k < per_xcd; ++k) heap.push({0.0, x + 8 * k});
-    for (const Job& jb : js) {
-      Slot s = heap.top();
-      heap.pop();
-      wjobs[(size_t)s.second].push_back(jb);
-      heap.push({s.first + jb.cost, s.second});
-    }
+    for (const Job& jb : js) items.push_back({jb.prob, jb.tm, jb.tn});
   }
-  std::vector<BatchItem> items;
-  std::vector<int32_t> wg_start((size_t)grid + 1, 0);
-  for (int w = 0; w < grid; ++w) {
-    wg_start[(size_t)w] = (int32_t)items.size();
-    for (const Job& jb : wjobs[(size_t)w]) items.push_back({jb.prob, jb.tm, jb.tn});
-  }
-  wg_start[(size_t)grid] = (int32_t)items.size();
+  q_start[kXcds] = (int32_t)items.size();
   bp->grid = grid;
   bp->n_items = (int64_t)items.size();
-  // one device allocation: probs | items | wg_start | scale list | pool
+  // one device allocation: probs | items | queue starts and counters | scale list | pool
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t s_probs = align(probs.size() * sizeof(BatchProblemDev) + 1);
   const size_t s_items = align(items.size() * sizeof(BatchItem) + 1);
-  const size_t s_wg = align(wg_start.size() * sizeof(int32_t));
+  const size_t s_wg = align((q_start.size() + 2 * kXcds) * sizeof(int32_t));  // counters start at zero
   const size_t s_scale = align(bp->scale_only.size() * sizeof(int32_t) + 1);
   const size_t s_pool = align(pool.size() * sizeof(uint32_t) + 1);
   const size_t total = s_probs + s_items + s_wg + s_scale + s_pool;
@@ -333,7 +333,7 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   std::memset(host, 0, total);
   std::memcpy(host, probs.data(), probs.size() * sizeof(BatchProblemDev));
   std::memcpy(host + s_probs, items.data(), items.size() * sizeof(BatchItem));
-  std::memcpy(host + s_probs + s_items, wg_start.data(), wg_start.size() * sizeof(int32_t));
+  std::memcpy(host + s_probs + s_items, q_start.data(), q_start.size() * sizeof(int32_t));
   std::memcpy(host + s_probs + s_items + s_wg, bp->scale_only.data(), bp->scale_only.size() * sizeof(int32_t));
   std::memcpy(host + s_probs + s_items + s_wg + s_scale, pool.data(), pool.size() * sizeof(uint32_t));
   e = hipMemcpy(bp->d_buf, host, total, hipMemcpyHostToDevice);
@@ -344,7 +344,9 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   }
   bp->args.probs = reinterpret_cast<const BatchProblemDev*>(base);
   bp->args.items = reinterpret_cast<const BatchItem*>(base + s_probs);
-  bp->args.wg_start = reinterpret_cast<const int32_t*>(base + s_probs + s_items);
+  bp->args.q_start = reinterpret_cast<const int32_t*>(base + s_probs + s_items);
+  bp->args.counters = reinterpret_cast<int32_t*>(base + s_probs + s_items) + q_start.size();
+  bp->args.per_queue = grid / kXcds;
   bp->args.pool = reinterpret_cast<const uint32_t*>(base + s_probs + s_items + s_wg + s_scale);
   bp->scale_dev = reinterpret_cast<const int32_t*>(base + s_probs + s_items + s_wg);
   auto* p = new (std::nothrow) famlies_plan_s();
