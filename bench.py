@@ -3,8 +3,10 @@
 Workloads (synthetic, seeded):
   ladder    (default) C[a,b,i,j] += sum_{e,f} W[a,b,e,f] T[e,f,i,j], v=128, o=32,
             W stored in mode order (e,a,f,b); FP64 headline, FP32 secondary.
-  ladder3   the same ladder at v=192, o=48 with outliers: FP32 vs bf16x3.
-  ring      C[a,i,b,j] = sum_{k,c} X[a,k,i,c] Y[c,b,k,j], o=48, v=192: FP32 vs bf16x3.
+  ladder3   the same ladder at v=192, o=48 with outliers: bf16x3 against FP32,
+            bf16x6 and FP64 on the same data.
+  ring      C[a,i,b,j] = sum_{k,c} X[a,k,i,c] Y[c,b,k,j], o=48, v=192: the same
+            four precisions.
   batched   20,000 random 4-index FP32 contractions, one persistent launch
             replayed from a HIP graph.
   autograd  forward + backward (dA, dB) of C[a,b,i,j] = sum A[a,e,i,f] B[e,b,f,j],
@@ -392,6 +394,13 @@ def _fp32_vs_bf16x3(args, p, name):
                                    "error_vs_fp64": sample_check(p, got, "f32", n=512)}
             log("%s bf16x3 packed A and B: pack %.2f ms once, %.3f ms/step" % (name, pack_ms, pms))
         s.close()
+    # the same data in FP64 (the FP32 values, exact in FP64) on the FP64 kernel
+    s = Single(p, "f64", "native")
+    check = sample_check(p, s.result_once(), "f64", n=1024)
+    ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
+    res["f64"] = {"ms": ms, "launch": launch, "info": s.info, "check": check}
+    log("%s f64: %.3f ms (%.1f GFLOP/s) check %s" % (name, ms, s.info["flops"] / ms / 1e6, check))
+    s.close()
     r3, r32 = res["bf16x3"], res["native"]
     flops = r3["info"]["flops"]
     out = base_record(args, flops / (r3["ms"] * 1e-3) / 1e9, r3["ms"], "bf16x3",
@@ -413,6 +422,12 @@ def _fp32_vs_bf16x3(args, p, name):
                      "value": round(flops / (r6["ms"] * 1e-3) / 1e9, 2),
                      "speedup_vs_fp32": round(r32["ms"] / r6["ms"], 3),
                      "error_vs_fp64": r6["check"]}
+    r64 = res["f64"]
+    out["fp64"] = {"ms_per_step": round(r64["ms"], 4),
+                   "value": round(flops / (r64["ms"] * 1e-3) / 1e9, 2),
+                   "pct_mfma_peak": round(100 * flops / (r64["ms"] * 1e-3) / PEAK["f64"], 2),
+                   "error_vs_fp64": r64["check"]}
+    out["bf16x3_speedup_vs_fp64"] = round(r64["ms"] / r3["ms"], 3)
     out["roofline"] = roofline(3 * flops, r3["launch"], PEAK["bf16"])
     return out
 
