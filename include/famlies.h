@@ -39,7 +39,9 @@
  * planning and may be freed afterwards.  A plan owns its device copies of
  * the indexing vectors and any split-K workspace; famlies_execute and
  * famlies_batch_execute allocate nothing and never synchronise, so they may
- * be captured into a HIP graph.  A handle must outlive its plans.
+ * be captured into a HIP graph.  A handle must outlive its plans.  Launches
+ * of one plan share its workspace (split-K partial sums, the batched work
+ * queues): they must not overlap in time (one stream, or ordered streams).
  *
  * Streams are passed as void* (a hipStream_t; NULL = the default stream).
  */
@@ -159,10 +161,11 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor *A,
                                famlies_plan_info *info, int64_t *offsets, int64_t offsets_len);
 
 /* Batched: n independent contractions (descriptor arrays of length n) of one
- * dtype, run by one persistent kernel over a device work list of
- * (problem, tile) items, tile shapes per size class from the handle's tile
- * table (tiles and orientation as in famlies_plan_contract; each descriptor
- * obeys the same rules).  Tensors of different problems may share memory
+ * dtype, run by one persistent kernel over device work queues of
+ * (problem, tile) items (one queue per XCD, drawn with an atomic counter
+ * that the kernel clears again before it ends), tile shapes per size class
+ * from the handle's tile table (tiles and orientation as in
+ * famlies_plan_contract; each descriptor obeys the same rules).  Tensors of different problems may share memory
  * for A and B; C outputs must be disjoint (not checked).  Batch modes are
  * UNSUPPORTED in batched plans. */
 famlies_status famlies_batch_plan(famlies_handle h, famlies_plan *out, int dtype, int64_t n,
