@@ -105,3 +105,40 @@ def test_tail_split_same_bits_as_whole_split(gpu, tmp_path):
     split_mask = t >= tm * -(-N // 64) - 4
     np.testing.assert_array_equal(outs["tail"][addr[split_mask]], outs["all"][addr[split_mask]])
     np.testing.assert_array_equal(outs["tail"][addr[~split_mask]], outs["whole"][addr[~split_mask]])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("split,tail", [(3, 0), (3, 2), (2, 5)])
+def test_tail_split_affine_short_units(gpu, tmp_path, dtype, split, tail):
+    """Both operands read in affine 16-byte blocks (two slices in flight) with
+    K = 96 cut into K slices of one or two slices each: the pipeline's
+    prologue and its clamped look-ahead loads on the shortest ranges."""
+    fm = gpu.fm
+    ext = {"k": 96, "i": 200, "j": 136}
+    lays = [synth.layout([ext[ch] for ch in lab]) for lab in ("ki", "kj", "ij")]
+    p = synth.Problem("affine_short", "ki", "kj", "ij", *lays, 1.0, 0.25)
+    rng = np.random.default_rng(47)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
+    p = round_inputs(p, dtype)
+    code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
+    bk = 16 if dtype == "f64" else 32
+    descs = [fm.make_desc(t.extents, t.strides, lab) for t, lab in ((p.a, p.la), (p.b, p.lb), (p.c, p.lc))]
+    info, _ = fm.famlies_analyze(code, 0, *descs)
+    lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
+    path = tmp_path / "short.txt"
+    path.write_text("plain %d 0 %d %d %d 64 64 %d %d 0 %d\n" % (code, lg(info["m"]), lg(info["n"]), lg(info["k"]),
+                                                               bk, split, tail))
+    h = fm.famlies_create(0)
+    fm.famlies_load_tune_table(h, str(path))
+    plan = fm.famlies_plan_contract(h, code, 0, *descs)
+    pi = fm.famlies_plan_get_info(plan)
+    note("affine short units %s: kernel %d split %d split tiles %d" % (dtype, pi["kernel"], pi["split_k"],
+                                                                       pi["split_tiles"]))
+    try:
+        assert pi["kernel"] & 48 == 48 and pi["split_k"] == split
+        want, d = oracle_full(p)
+        got = gpu.run(p, dtype, plan=plan)
+        (check_fp64 if dtype == "f64" else check_fp32)(got, want, d, 96)
+    finally:
+        fm.famlies_plan_destroy(plan)
+        fm.famlies_destroy(h)
