@@ -143,3 +143,27 @@ def test_bf16x6_fp32_level_accuracy(gpu, case):
     e32 = np.linalg.norm(f32[u] - exact[u]) / np.linalg.norm(exact[u])
     note("%s K=%d  bf16x6 rel err %.3e   fp32 rel err %.3e" % (case, K, e6, e32))
     assert e6 < 4 * e32 + 1e-7
+
+
+@pytest.mark.parametrize("compute", ["bf16x3", "bf16x6"])
+@pytest.mark.parametrize("k", [32, 64, 96, 40])
+def test_split_kernels_short_k(gpu, compute, k):
+    """Short K on the split kernels' two-slice pipeline (one, two and three
+    slices; K = 40 also has a partial last slice and is gathered): each
+    result agrees with the oracle's split-exact reference up to the FP32
+    accumulation."""
+    ext = {"k": k, "i": 200, "j": 136}
+    lays = [synth.layout([ext[ch] for ch in lab]) for lab in ("ki", "kj", "ij")]
+    p = synth.Problem("short_k", "ki", "kj", "ij", *lays, 1.0, 0.5)
+    rng = np.random.default_rng(90 + k)
+    p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "outliers") for t in (p.a, p.b, p.c))
+    p = round_inputs(p, "f32")
+    args = (p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:])
+    exact, d = oracle.contract(*args, want_cond=True)
+    ref = oracle.contract(*args, split=1 if compute == "bf16x3" else 2)
+    dp = _d_prod(p)
+    got = gpu.run(p, "f32", compute=compute)
+    parts = 2 if compute == "bf16x3" else 3
+    acc = gamma(parts * k, 2.0 ** -23) * (1 + 2.0 ** -7) * dp + 2.0 ** -23 * d
+    np.testing.assert_array_less(np.abs(got - ref), acc + 1e-300)
+    note("%s K=%d max |got-ref|/D %.2e" % (compute, k, float(np.max(np.abs(got - ref) / np.maximum(d, 1e-300)))))
