@@ -347,12 +347,20 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     // bf16x3 on large problems: a 256 x 128 tile (128 x 64 per wave) halves
     // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 has three
     // accumulators per block and stays at 128 x 128).  It has registers for
-    // one slice in flight only, so it is taken when both operands are read
-    // along K; a row-gathered operand keeps the 128 x 128 tile with two
-    // slices in flight (ring o=48 v=192: 186 -> 201 TFLOP/s FP32-equivalent).
+    // one slice in flight and one workgroup per CU, so it is taken only when
+    // both operands are element-gathered along K: a row-gathered operand
+    // keeps the 128 x 128 tile with two slices in flight (ring o=48 v=192:
+    // 186 -> 201 TFLOP/s FP32-equivalent), and an affine-block operand the
+    // 128 x 128 tile at two workgroups per CU (ladder v=128 o=32: 284 -> 307).
     if (!force && ns == 2 && an.M >= 1024 && an.N >= 512 && p->cfg.split == 1 && an.x_kfast && an.y_kfast) {
-      p->cfg.bm = 256;
-      p->cfg.bn = 128;
+      std::vector<int64_t> v[9];
+      bool xv = false, yv = false;
+      all_offsets(an, v);
+      vec_flags(an, 32, index_bits_for(an), v, &xv, &yv);
+      if (!xv && !yv) {
+        p->cfg.bm = 256;
+        p->cfg.bn = 128;
+      }
     }
     if (!split_tile_supported(ns, p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
   } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
