@@ -180,18 +180,23 @@ struct SplitLoader<OffT, BR, NS, kPacked, NSLOT> {
 template <typename OffT, int BM, int NS, int XM, int YM>
 constexpr int kSplitDepth = BM == 256 ? 1 : 2;
 
-// Two workgroups per CU for the 128 x 128 bf16x3 tile when its operands
-// are read along K in affine blocks or pre-packed (they then fit in 256
-// registers with two slices in flight, and two tiles' LDS in the CU's
-// 160 KB); measured: ring with pre-packed operands 254 -> 330, ladder
-// v=192 o=48 260 -> 275 TFLOP/s FP32-equivalent.  Row-gathered operands,
-// both operands element-gathered along K, and the other tiles would spill.
-template <int BM, int NS, int XM, int YM>
+// Two workgroups per CU for the 128 x 128 bf16x3 tile (256 registers per
+// lane, two tiles' LDS in the CU's 160 KB) when its operands are read along
+// K in affine blocks or pre-packed: they then fit with two slices in flight;
+// measured: ring with pre-packed operands 254 -> 330, ladder v=192 o=48
+// 260 -> 275 TFLOP/s FP32-equivalent.  With 32-bit offsets one row-gathered
+// operand is also allowed: that spills 5 to 24 registers, yet the second
+// workgroup hides more than the spills cost (ring, A read along K in affine
+// blocks and B row-gathered: 195 -> 251).  Both operands row-gathered or
+// both element-gathered along K, 64-bit offsets with a row-gathered operand
+// (74 to 111 registers spilled) and the other tiles stay at one.
+template <typename OffT, int BM, int NS, int XM, int YM>
 constexpr int kSplitWgPerCu =
-    (BM == 128 && NS == 2 && XM != kRowGather && YM != kRowGather && !(XM == kKGather && YM == kKGather)) ? 2 : 1;
+    (BM == 128 && NS == 2 && !(XM == kKGather && YM == kKGather) && !(XM == kRowGather && YM == kRowGather) &&
+     ((XM != kRowGather && YM != kRowGather) || sizeof(OffT) == 4)) ? 2 : 1;
 
 template <typename OffT, int BM, int BN, int XM, int YM, int NS>
-__global__ __launch_bounds__(kThreads, (kSplitWgPerCu<BM, NS, XM, YM>)) void split_contract(PlainArgs<OffT> a) {
+__global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) void split_contract(PlainArgs<OffT> a) {
   constexpr int BK = kB3K;
   // Slices in flight: one workgroup per CU holds the accumulators, so the
   // next slice's loads must hide behind a single slice of bf16 MFMAs; two
