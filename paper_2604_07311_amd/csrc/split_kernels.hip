@@ -181,15 +181,15 @@ template <typename OffT, int BM, int NS, int XM, int YM>
 constexpr int kSplitDepth = BM == 256 ? 1 : 2;
 
 // Two workgroups per CU for the 128 x 128 bf16x3 tile (256 registers per
-// lane, two tiles' LDS in the CU's 160 KB) when its operands are read along
-// K in affine blocks or pre-packed: they then fit with two slices in flight;
-// measured: ring with pre-packed operands 254 -> 330, ladder v=192 o=48
-// 260 -> 275 TFLOP/s FP32-equivalent.  With 32-bit offsets one row-gathered
+// lane, two tiles' LDS in the CU's 160 KB) when its operands are read along K
+// in affine blocks or pre-packed: they then fit with two slices in flight;
+// measured: ring with pre-packed operands 254 -> 330, ladder v=192 o=48 260
+// -> 275 TFLOP/s FP32-equivalent.  With 32-bit offsets one row-gathered
 // operand is also allowed: that spills 5 to 24 registers, yet the second
 // workgroup hides more than the spills cost (ring, A read along K in affine
-// blocks and B row-gathered: 195 -> 251).  Both operands row-gathered or
-// both element-gathered along K, 64-bit offsets with a row-gathered operand
-// (74 to 111 registers spilled) and the other tiles stay at one.
+// blocks and B row-gathered: 201 -> 261 TFLOP/s).  Both operands row-gathered
+// or both element-gathered along K, 64-bit offsets with a row-gathered
+// operand (74 to 111 registers spilled) and the other tiles stay at one.
 template <typename OffT, int BM, int NS, int XM, int YM>
 constexpr int kSplitWgPerCu =
     (BM == 128 && NS == 2 && !(XM == kKGather && YM == kKGather) && !(XM == kRowGather && YM == kRowGather) &&
