@@ -31,8 +31,20 @@
  *   - Results are deterministic run to run (no floating-point atomics).
  *
  * Errors: every call returns a famlies_status; nothing aborts or throws
- * across the ABI.  famlies_last_error() returns a thread-local message for
- * the last failing call on the calling thread (valid until the next call).
+ * across the ABI (a host allocation failure during planning is reported as
+ * FAMLIES_ERR_ALLOC).  famlies_last_error() returns a thread-local message
+ * for the last failing call on the calling thread (valid until the next
+ * call).
+ *
+ * Handles, plans and networks are opaque, generation-counted tokens, not
+ * addresses: a destroyed object's token, a token of another kind or a
+ * made-up value is rejected with FAMLIES_ERR_INVALID_ARG (code safety and
+ * graceful errors: Girder 1, "Code safety").
+ *
+ * Logging: with the environment variable FAMLIES_LOG set (not "0"), every
+ * plan and planner dry run writes one line to stderr with what the planner
+ * decided (sizes, orientation, loaders, tile, split-K, index width,
+ * workspace).
  *
  * Ownership: the caller owns all tensor memory (device memory for data,
  * host memory for descriptors).  Descriptor arrays are copied during
@@ -66,6 +78,8 @@ typedef int32_t famlies_status;
 #define FAMLIES_ERR_ALIGN (-6)          /* data pointer not aligned to its element size */
 #define FAMLIES_ERR_ALLOC (-7)          /* device allocation failed */
 #define FAMLIES_ERR_DEVICE (-8)         /* a HIP error (pending errors are reported, not cleared) */
+#define FAMLIES_ERR_BOUNDS (-9)         /* planner self-check: an indexing vector would address outside
+                                           its tensor's span (host-side, before any upload) */
 
 #define FAMLIES_MAX_RANK 8
 

@@ -21,6 +21,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+from collections import OrderedDict
 from typing import Dict, Optional, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +36,7 @@ FAMLIES_ERR_ALIAS = -5
 FAMLIES_ERR_ALIGN = -6
 FAMLIES_ERR_ALLOC = -7
 FAMLIES_ERR_DEVICE = -8
+FAMLIES_ERR_BOUNDS = -9
 FAMLIES_MAX_RANK = 8
 FAMLIES_F64 = 1
 FAMLIES_F32 = 2
@@ -46,6 +48,7 @@ ERROR_NAMES = {
     FAMLIES_ERR_INVALID_ARG: "INVALID_ARG", FAMLIES_ERR_SHAPE_MISMATCH: "SHAPE_MISMATCH",
     FAMLIES_ERR_LABEL: "LABEL", FAMLIES_ERR_UNSUPPORTED: "UNSUPPORTED", FAMLIES_ERR_ALIAS: "ALIAS",
     FAMLIES_ERR_ALIGN: "ALIGN", FAMLIES_ERR_ALLOC: "ALLOC", FAMLIES_ERR_DEVICE: "DEVICE",
+    FAMLIES_ERR_BOUNDS: "BOUNDS",
 }
 
 
@@ -326,10 +329,16 @@ def famlies_load_tune_table(handle: int, table_path: str) -> None:
 
 
 # ----------------------------------------------------------- torch-level API
-_state = threading.local()
 _handles: Dict[int, int] = {}
-_plan_cache: Dict[tuple, int] = {}
-_cache_lock = threading.Lock()
+# Plans keyed by device, stream, types, shapes, strides and labels.  A plan
+# owns a split-K workspace that its launches share, so one plan serves one
+# stream only: calls on unordered streams get plans of their own and never
+# write partial sums into the same workspace.  Least recently used plans are
+# destroyed beyond PLAN_CACHE_MAX entries (after the device has finished
+# with them; never while a graph is being captured).
+PLAN_CACHE_MAX = 256
+_plan_cache: "OrderedDict[tuple, int]" = OrderedDict()
+_cache_lock = threading.RLock()
 
 
 def _torch():
@@ -367,31 +376,52 @@ def _labels(l) -> Tuple[int, ...]:
     return tuple(ord(c) for c in l) if isinstance(l, str) else tuple(int(x) for x in l)
 
 
-def plan_for(A, la, B, lb, C, lc, compute: str = "native") -> int:
-    """Cached plan for tensors of these shapes, strides and labels."""
+def _evict_locked() -> None:
+    torch = _torch()
+    if len(_plan_cache) <= PLAN_CACHE_MAX:
+        return
+    if torch.cuda.is_available() and torch.cuda.is_current_stream_capturing():
+        return  # a captured graph may still refer to any cached plan
+    victims = []
+    while len(_plan_cache) > PLAN_CACHE_MAX:
+        key, p = _plan_cache.popitem(last=False)
+        victims.append((key[0], p))
+    for dev in {d for d, _ in victims}:
+        torch.cuda.synchronize(dev)  # launches still queued may use the plans
+    for _, p in victims:
+        famlies_plan_destroy(p)
+
+
+def plan_for(A, la, B, lb, C, lc, compute: str = "native", stream: int = 0) -> int:
+    """Cached plan for tensors of these shapes, strides and labels, to be
+    launched on `stream` (a raw stream handle)."""
     dev = C.device.index or 0
-    key = (dev, _dtype_code(C), _compute_code(compute),
+    key = (dev, int(stream), _dtype_code(C), _compute_code(compute),
            tuple(A.shape), tuple(A.stride()), _labels(la),
            tuple(B.shape), tuple(B.stride()), _labels(lb),
            tuple(C.shape), tuple(C.stride()), _labels(lc))
     with _cache_lock:
         p = _plan_cache.get(key)
-    if p is not None:
-        return p
-    p = famlies_plan_contract(handle(dev), key[1], key[2],
-                              make_desc(A.shape, A.stride(), la),
-                              make_desc(B.shape, B.stride(), lb),
-                              make_desc(C.shape, C.stride(), lc))
-    with _cache_lock:
+        if p is not None:
+            _plan_cache.move_to_end(key)
+            return p
+        p = famlies_plan_contract(handle(dev), key[2], key[3],
+                                  make_desc(A.shape, A.stride(), la),
+                                  make_desc(B.shape, B.stride(), lb),
+                                  make_desc(C.shape, C.stride(), lc))
         _plan_cache[key] = p
-    return p
+        _evict_locked()
+        return p
 
 
 def clear_plan_cache() -> None:
     with _cache_lock:
-        plans = list(_plan_cache.values())
+        plans = list(_plan_cache.items())
         _plan_cache.clear()
-    for p in plans:
+    torch = _torch()
+    for dev in {k[0] for k, _ in plans}:
+        torch.cuda.synchronize(dev)
+    for _, p in plans:
         famlies_plan_destroy(p)
 
 
@@ -420,8 +450,8 @@ def contract(alpha: float, A, la, B, lb, beta: float = 0.0, C=None, lc=None, *,
             raise TypeError("famlies.contract needs GPU tensors (no CPU fallback)")
     if not (A.dtype == B.dtype == C.dtype):
         raise TypeError("A, B and C must share one dtype")
-    p = plan_for(A, la, B, lb, C, lc, compute)
     s = stream if stream is not None else torch.cuda.current_stream(C.device)
+    p = plan_for(A, la, B, lb, C, lc, compute, s.cuda_stream)
     famlies_execute(p, alpha, A.data_ptr(), B.data_ptr(), beta, C.data_ptr(), s.cuda_stream)
     return C
 

@@ -10,6 +10,20 @@ Both gradients are themselves labelled contractions, so they run on the
 same planner and kernels as the forward (the paper's aim of one engine
 reused across operations, Section "Building on important advances", BLIS
 2.0 building blocks; ML use of tensor operations, "Project Motivation").
+dC0 is G copied into C0's layout and scaled by the engine's own C update
+(a contraction with alpha = 0).
+
+Labels that the forward folds into the GEMM view need one more step on the
+way back:
+
+* a label repeated within an input (a diagonal): the gradient is zero off
+  the diagonal, so the gradient tensor is zero-filled and the contraction
+  writes into its diagonal view (one mode per distinct label, strides of
+  the repeats summed -- injective whenever the input's layout is);
+* a label only in that input (summed inside it): the gradient does not
+  depend on it, so the contraction runs without it and its result is
+  broadcast along it.
+
 The Function is functional: it never writes into C0.  Gradients take their
 input's strides when that input is dense (torch's preserve_format), so the
 engine accumulates them without a layout copy.
@@ -21,6 +35,41 @@ import torch
 from . import contract as _contract
 
 
+def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first):
+    """Gradient with respect to `target` (labels lt): alpha times the
+    contraction of G (labels lc) with the other operand (labels lo) onto
+    target's labels, in a tensor laid out like target."""
+    lt = list(lt)
+    uniq = []
+    for ch in lt:
+        if ch not in uniq:
+            uniq.append(ch)
+    kept = [ch for ch in uniq if ch in lc or ch in lo]
+
+    def run(out, labels):
+        if g_first:
+            return _contract(alpha, G, lc, other, lo, 0.0, out, labels, compute=compute)
+        return _contract(alpha, other, lo, G, lc, 0.0, out, labels, compute=compute)
+
+    if len(uniq) == len(lt) and len(kept) == len(uniq):
+        grad = torch.empty_like(target, memory_format=torch.preserve_format)
+        run(grad, lt)
+        return grad
+    grad = torch.zeros_like(target, memory_format=torch.preserve_format)
+    ext = {ch: target.shape[i] for i, ch in enumerate(lt)}
+    stride = {ch: 0 for ch in uniq}
+    for i, ch in enumerate(lt):
+        stride[ch] += grad.stride(i)
+    view = grad.as_strided([ext[ch] for ch in uniq], [stride[ch] for ch in uniq], grad.storage_offset())
+    if len(kept) == len(uniq):
+        run(view, uniq)
+    else:
+        red = run(None, kept)  # dense, modes in `kept` order (a subsequence of `uniq`)
+        shape = [ext[ch] if ch in kept else 1 for ch in uniq]
+        view.copy_(red.reshape(shape).expand(view.shape))
+    return grad
+
+
 class ContractFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, alpha, A, la, B, lb, beta, C0, lc, compute="native"):
@@ -29,23 +78,26 @@ class ContractFn(torch.autograd.Function):
             _contract(alpha, A.detach(), la, B.detach(), lb, beta, C, lc, compute=compute)
         else:
             C = _contract(alpha, A.detach(), la, B.detach(), lb, 0.0, None, lc, compute=compute)
-        ctx.save_for_backward(A, B)
+        ctx.save_for_backward(A, B, C0 if C0 is not None else None)
         ctx.cfg = (alpha, la, lb, beta, lc, compute, C0 is not None)
         return C
 
     @staticmethod
     def backward(ctx, G):
-        A, B = ctx.saved_tensors
+        A, B, C0 = ctx.saved_tensors
         alpha, la, lb, beta, lc, compute, has_c0 = ctx.cfg
         dA = dB = dC0 = None
         if ctx.needs_input_grad[1]:
-            dA = torch.empty_like(A, memory_format=torch.preserve_format)
-            _contract(alpha, G, lc, B.detach(), lb, 0.0, dA, la, compute=compute)
+            dA = _operand_grad(alpha, G, lc, B.detach(), lb, A, la, compute, True)
         if ctx.needs_input_grad[3]:
-            dB = torch.empty_like(B, memory_format=torch.preserve_format)
-            _contract(alpha, A.detach(), la, G, lc, 0.0, dB, lb, compute=compute)
+            dB = _operand_grad(alpha, G, lc, A.detach(), la, B, lb, compute, False)
         if has_c0 and ctx.needs_input_grad[6]:
-            dC0 = G * beta
+            dC0 = torch.empty_like(C0, memory_format=torch.preserve_format)
+            if beta != 0.0:
+                dC0.copy_(G)
+            # alpha = 0: the engine's C update alone, dC0 = beta * dC0 (zeros
+            # when beta == 0, without reading dC0)
+            _contract(0.0, A.detach(), la, B.detach(), lb, beta, dC0, lc, compute=compute)
         return None, dA, None, dB, None, None, dC0, None, None
 
 

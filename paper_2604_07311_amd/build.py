@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libfamlies.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["abi.hip", "planner.cpp", "table.cpp", "plain_kernels.hip", "split_kernels.hip",
-           "batch.hip", "tune.hip", "pack_kernels.hip", "network.cpp"]
+           "batch.hip", "tune.hip", "pack_kernels.hip", "network.cpp", "registry.cpp", "plan_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("FAMLIES_CXX", "/opt/rocm/lib/llvm/bin/clang++")
@@ -26,10 +26,21 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + INCLUDE, "-I" + CSRC, "-Wall",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+    return max(os.path.getmtime(h) for h in hs)
+
+
 def _compile(src: str, extra=()) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
+    # FAMLIES_INCREMENTAL=1 (development only) keeps objects newer than their
+    # source and every header; the default rebuilds everything.
+    if os.environ.get("FAMLIES_INCREMENTAL") == "1" and not extra and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(path), _headers_mtime()):
+        return obj
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + DEVICE + COMMON + list(extra) + ["-c", path, "-o", obj]
     else:  # host-only C++

@@ -22,32 +22,8 @@
 
 namespace famlies {
 
-static thread_local std::string g_err;
-void set_error(const std::string& msg) { g_err = msg; }
-
-static std::mutex g_live_mu;
-static std::set<const void*> g_live;  // live handles and plans (use-after-destroy check)
-
-void register_live(const void* p) {
-  std::lock_guard<std::mutex> lk(g_live_mu);
-  g_live.insert(p);
-}
-void unregister_live(const void* p) {
-  std::lock_guard<std::mutex> lk(g_live_mu);
-  g_live.erase(p);
-}
-bool is_live(const void* p) {
-  std::lock_guard<std::mutex> lk(g_live_mu);
-  return g_live.count(p) != 0;
-}
-
-famlies_status fail(famlies_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
 famlies_status hip_fail(hipError_t e, const char* what) {
-  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
   return e == hipErrorOutOfMemory ? FAMLIES_ERR_ALLOC : FAMLIES_ERR_DEVICE;
 }
 
@@ -59,176 +35,6 @@ DeviceGuard::DeviceGuard(int device) {
 }
 DeviceGuard::~DeviceGuard() {
   if (prev >= 0) (void)hipSetDevice(prev);
-}
-
-static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-// Step a4: tile shape and split-K.  A tile-table entry for the problem's
-// size class wins.  Otherwise a small cost model picks the tile edge (128 or
-// 64) and the number of K slices: the workgroups are dealt to the CUs two at
-// a time (two share a CU at half rate each; a lone one runs at about 0.65 of
-// the CU), so the busiest CU's time is
-//     pairs * 2w + (odd ? w / 0.65 : 0),  w = work of one workgroup,
-// a 64-edge tile does its flops at about 0.75 of the 128-edge rate, and each
-// extra K slice costs a pass over the split tiles' partial sums (at HBM
-// rate, measured in the same units).  Splitting is either whole (every tile
-// in K slices) or of the tail only: when the tiles fill some rounds of two
-// workgroups per CU and part of one more, the whole rounds run unsplit and
-// only the tiles of the last round are cut into K slices, so that round
-// spreads over every CU instead of leaving most of them idle.  The model
-// only ranks candidates; it is not a timing.
-TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an) {
-  TileCfg t;
-  const int bk = an.dtype == FAMLIES_F64 ? 16 : 32;
-  t.bk = bk;
-  if (an.M == 0 || an.N == 0 || an.K == 0) return t;
-  if (h && h->table.lookup_plain(an, &t)) return t;
-  const int cus = h ? h->num_cus : 256;
-  // CU throughput in flop/s and HBM bandwidth in bytes/s (MI355X-class)
-  const double cu_rate = (an.dtype == FAMLIES_F64 ? 78.6e12 : 157.3e12) / 256.0;
-  const double hbm = 8.0e12 * cus / 256.0;
-  const double es = an.esize;
-  double best = 1e300;
-  TileCfg pick = t;
-  for (int bt : {128, 64}) {
-    const int64_t tiles = ceil_div(an.M, bt) * ceil_div(an.N, bt) * an.L;
-    const double eff = bt == 128 ? 1.0 : 0.75;
-    for (int split : {1, 2, 3, 4, 6, 8, 12, 16}) {
-      if (split > 1 && (an.L > 1 || an.K / split < 2 * bk)) continue;
-      const int64_t units = tiles * split;
-      const int64_t q = ceil_div(units, cus);  // workgroups on the busiest CU
-      const double w = 2.0 * bt * bt * ((double)an.K / split) / (cu_rate * eff);
-      double time = (double)(q / 2) * 2.0 * w + (q % 2 ? w / 0.65 : 0.0);
-      if (split > 1) time += (double)split * an.M * an.N * es * 2.0 / hbm + 4e-6;
-      if (time < best * 0.9) {  // prefer fewer slices / larger tiles unless clearly faster
-        best = time;
-        pick.bm = pick.bn = bt;
-        pick.split = split;
-        pick.tail = 0;
-      }
-    }
-    // tail split: whole rounds unsplit, the last partial round in K slices
-    const int64_t slots = 2 * (int64_t)cus, rem = tiles % slots;
-    if (an.L == 1 && tiles > slots && rem > 0) {
-      const double w = 2.0 * bt * bt * (double)an.K / (cu_rate * eff);
-      const double head = (double)(tiles / slots) * 2.0 * w;
-      for (int split : {2, 3, 4, 6, 8}) {
-        if (an.K / split < 2 * bk) continue;
-        const int64_t q = ceil_div(rem * split, cus);
-        const double ws = w / split;
-        const double time = head + (double)(q / 2) * 2.0 * ws + (q % 2 ? ws / 0.65 : 0.0) +
-                            (double)split * rem * bt * bt * es * 2.0 / hbm + 4e-6;
-        if (time < best * 0.95) {  // only the tail pays for partial sums
-          best = time;
-          pick.bm = pick.bn = bt;
-          pick.split = split;
-          pick.tail = (int)rem;
-        }
-      }
-    }
-  }
-  return pick;
-}
-
-// Settle split-K: K slices of whole BK-blocks, and the number of tiles
-// computed whole first (*head; every tile when there is no split).
-static void finalize_split(TileCfg* t, int64_t K, int64_t ntiles, int* kchunk, int* head) {
-  *head = (int)std::min<int64_t>(ntiles, INT32_MAX);
-  if (t->split <= 1 || K <= t->bk) {
-    t->split = 1;
-    t->tail = 0;
-    *kchunk = (int)std::max<int64_t>(K, 1);
-    return;
-  }
-  int64_t chunk = ceil_div(ceil_div(K, t->split), t->bk) * t->bk;
-  t->split = (int)ceil_div(K, chunk);
-  *kchunk = (int)chunk;
-  if (t->split <= 1) {
-    t->split = 1;
-    t->tail = 0;
-    *kchunk = (int)K;
-    return;
-  }
-  if (t->tail <= 0 || t->tail >= ntiles) t->tail = 0;  // every tile split
-  *head = t->tail ? (int)(ntiles - t->tail) : 0;
-}
-
-static void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int kernel,
-                      famlies_plan_info* info) {
-  std::memset(info, 0, sizeof *info);
-  info->m = an.M;
-  info->n = an.N;
-  info->k = an.K;
-  info->batch = an.L;
-  info->n_batch = (int32_t)an.Lm.size();
-  info->n_trace = an.n_trace;
-  info->n_diag = an.n_diag;
-  info->swapped = an.swapped;
-  info->x_kfast = an.x_kfast;
-  info->y_kfast = an.y_kfast;
-  info->n_i = (int32_t)an.I.size();
-  info->n_j = (int32_t)an.J.size();
-  info->n_p = (int32_t)an.P.size();
-  info->tile_m = t.bm;
-  info->tile_n = t.bn;
-  info->tile_k = t.bk;
-  info->split_k = t.split;
-  info->split_tiles = t.split > 1 ? (t.tail ? t.tail : (int32_t)(ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn))) : 0;
-  info->index_bits = index_bits;
-  info->kernel = kernel;
-  info->flops = 2.0 * (double)an.L * (double)an.M * (double)an.N * (double)an.K;
-}
-
-// 32: uint32 byte offsets from each operand's lowest element (every operand
-// spans less than 4 GiB over its non-batch modes); 64: int64 element offsets.
-static int index_bits_for(const Analysis& an) {
-  const int64_t lim = ((int64_t)1 << 32) - 64;
-  const int64_t es = an.esize;
-  return ((an.x_span + 1) * es < lim && (an.y_span + 1) * es < lim && (an.c_span + 1) * es < lim) ? 32 : 64;
-}
-
-// Upload the indexing vectors (padded to the tile grid) into one device
-// buffer: six OffT vectors (X rows, X k, Y k, Y cols, C rows, C cols), then
-// the three int64 batch-offset vectors.  In the uint32 form every row vector
-// is rebased by its operand's lowest offset and all six are scaled to bytes;
-// sums row + col then land in [0, span) (unsigned wrap-around is exact).
-// Block strides of the block-scatter layout (Approach, "Supporting tensor
-// computations"): an operand gathered along K can be read with 16-byte loads
-// when BK divides K (every slice whole), in every BK-block of K its indexing
-// vector steps by exactly one element, and every run start (row offset +
-// block start + batch offset, in elements from the base pointer) is a
-// multiple of the 16-byte vector.
-static bool affine_k_blocks(const std::vector<int64_t>& rows, int64_t nrows, const std::vector<int64_t>& ks,
-                            int64_t K, int bk, const std::vector<int64_t>& batch, int64_t L, int64_t vk) {
-  if (K < 1 || K % bk) return false;
-  for (int64_t b = 0; b < K; b += bk) {
-    const int64_t s0 = ks[(size_t)b];
-    if (s0 % vk) return false;
-    for (int64_t k = b + 1; k < std::min<int64_t>(K, b + bk); ++k)
-      if (ks[(size_t)k] != s0 + (k - b)) return false;
-  }
-  for (int64_t m = 0; m < nrows; ++m)
-    if (rows[(size_t)m] % vk) return false;
-  for (int64_t l = 0; l < L; ++l)
-    if (batch[(size_t)l] % vk) return false;
-  return true;
-}
-
-// Affine-block flags of X and Y for a plan with K-slice depth bk; v holds
-// the nine indexing vectors in upload() order.
-static void vec_flags(const Analysis& an, int bk, int /*index_bits*/, const std::vector<int64_t>* v, bool* xv,
-                      bool* yv) {
-  *xv = *yv = false;
-  const int64_t vk = 16 / an.esize;
-  *xv = an.x_kfast && affine_k_blocks(v[0], an.M, v[1], an.K, bk, v[6], an.L, vk);
-  *yv = an.y_kfast && affine_k_blocks(v[3], an.N, v[2], an.K, bk, v[7], an.L, vk);
-}
-
-static void all_offsets(const Analysis& an, std::vector<int64_t>* v) {
-  const std::vector<Mode>* groups[9] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J, &an.Lm, &an.Lm, &an.Lm};
-  const int which[9] = {0, 0, 1, 1, 2, 2, 0, 1, 2};
-  const int64_t len[9] = {an.M, an.K, an.K, an.N, an.M, an.N, an.L, an.L, an.L};
-  for (int i = 0; i < 9; ++i) offsets(*groups[i], which[i], len[i], len[i], v[i]);
 }
 
 template <typename OffT>
@@ -270,6 +76,13 @@ static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t 
     for (int64_t l = 0; l < an.L; ++l) lb[i * an.L + l] = v[6 + i][(size_t)l];
   }
   p->batch_off_bytes = b6;
+  // host-side bounds check of the vectors against the descriptors' spans
+  const int64_t x_lo = an.swapped ? an.b_lo : an.a_lo, x_hi = an.swapped ? an.b_hi : an.a_hi;
+  const int64_t y_lo = an.swapped ? an.a_lo : an.b_lo, y_hi = an.swapped ? an.a_hi : an.b_hi;
+  if ((an.K > 0 && (!offsets_in_span(v[0], an.M, v[1], an.K, v[6], an.L, x_lo, x_hi) ||
+                    !offsets_in_span(v[3], an.N, v[2], an.K, v[7], an.L, y_lo, y_hi))) ||
+      !offsets_in_span(v[4], an.M, v[5], an.N, v[8], an.L, an.c_lo, an.c_hi))
+    return fail(FAMLIES_ERR_BOUNDS, "planner: an indexing vector addresses outside its tensor's span");
   hipError_t e = hipMalloc(&p->d_off, total);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(indexing vectors)");
   e = hipMemcpy(p->d_off, host.data(), total, hipMemcpyHostToDevice);
@@ -320,21 +133,27 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
                          const TileCfg* force) {
   if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
   *out = nullptr;
-  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
   Analysis an;
   std::string err;
   int st = analyze(dtype, compute, A, B, C, &an, &err);
   if (st != FAMLIES_OK) return fail(st, err);
-  const int64_t lim = ((int64_t)1 << 31) - 1024;
+  const int64_t lim = kMaxGemmDim;
   if (an.M > lim || an.N > lim || an.K > lim || an.L > lim)
     return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
   DeviceGuard dg(h->device);
   if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
   auto* p = new (std::nothrow) famlies_plan_s();
   if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  struct Owner {  // frees the plan if planning throws (host allocation failure)
+    famlies_plan_s** q;
+    ~Owner() {
+      if (*q) delete *q;
+    }
+  } owner{&p};
   p->h = h;
   p->an = an;
-  p->cfg = force ? *force : choose_tiles(h, an);
+  p->cfg = force ? *force : choose_tiles(h, an, &p->table_hit);
   p->index_bits = p->cfg.index_bits == 64 ? 64 : index_bits_for(an);
   const int ns = split_parts(compute);
   if (ns) {
@@ -371,7 +190,6 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   const int64_t ntiles = ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn);
   finalize_split(&p->cfg, an.K, ntiles, &p->kchunk, &p->head);
   if (ntiles * p->cfg.split * an.L >= ((int64_t)1 << 31)) {
-    delete p;
     return fail(FAMLIES_ERR_UNSUPPORTED, "the tile grid exceeds 2^31 workgroups");
   }
   const bool empty = an.M == 0 || an.N == 0;
@@ -381,7 +199,6 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
     const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
     st = p->index_bits == 32 ? upload<uint32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
     if (st != FAMLIES_OK) {
-      delete p;
       return st;
     }
     if (p->cfg.split > 1 && an.K > 0) {
@@ -392,16 +209,25 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
                                (size_t)p->cfg.bn * (size_t)an.esize;
       hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
       if (e != hipSuccess) {
-        delete p;
         return hip_fail(e, "hipMalloc(split-K workspace)");
       }
     }
   }
-  register_live(p);
+  if (log_enabled()) log_plan(p);
   *out = p;
+  p = nullptr;  // owned by the caller now
   return FAMLIES_OK;
 }
 
+void log_plan(const famlies_plan_s* p) {
+  log_decision("plan", p->an, p->cfg, p->index_bits, p->x_vec, p->y_vec, p->work_bytes, p->table_hit);
+}
+
+void destroy_plan(famlies_plan_s* p) {
+  if (!p) return;
+  DeviceGuard dg(p->h->device);
+  delete p;
+}
 
 }  // namespace famlies
 
@@ -414,8 +240,6 @@ famlies_plan_s::~famlies_plan_s() {
 using namespace famlies;
 
 extern "C" {
-
-const char* famlies_last_error(void) { return g_err.c_str(); }
 
 const char* famlies_version(void) { return "famlies-mi355x 0.1 (gfx950)"; }
 
@@ -444,70 +268,50 @@ famlies_status famlies_create(famlies_handle* out, int device) {
       return fail(FAMLIES_ERR_INVALID_ARG, "FAMLIES_TUNE_TABLE: " + err);
     }
   }
-  register_live(h);
-  *out = h;
+  void* tok = registry_add(h, ObjKind::kHandle);
+  if (!tok) {
+    delete h;
+    return fail(FAMLIES_ERR_ALLOC, "famlies_create: no free object slot");
+  }
+  *out = static_cast<famlies_handle>(tok);
   return FAMLIES_OK;
 }
 
-famlies_status famlies_destroy(famlies_handle h) {
-  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_destroy: invalid handle");
-  unregister_live(h);
+famlies_status famlies_destroy(famlies_handle tok) {
+  auto* h = static_cast<famlies_handle_s*>(registry_take(tok, ObjKind::kHandle));
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_destroy: invalid handle");
   delete h;
   return FAMLIES_OK;
 }
 
-famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tensor* B,
-                               const famlies_tensor* C, famlies_plan_info* info, int64_t* offs,
-                               int64_t offs_len) {
-  if (!info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: null info");
-  Analysis an;
-  std::string err;
-  int st = analyze(dtype, compute, A, B, C, &an, &err);
-  if (st != FAMLIES_OK) return fail(st, err);
-  TileCfg t = choose_tiles(nullptr, an);
-  if (split_parts(an.compute) && t.tail) {  // as in make_plan: no split for the bf16 kernels
-    t.split = 1;
-    t.tail = 0;
-  }
-  int kchunk = 0, head = 0;
-  finalize_split(&t, an.K, ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn), &kchunk, &head);
-  const int ib = index_bits_for(an);
-  std::vector<int64_t> v[9];
-  bool xv = false, yv = false;
-  if (an.M > 0 && an.N > 0) {
-    all_offsets(an, v);
-    vec_flags(an, t.bk, ib, v, &xv, &yv);
-  }
-  fill_info(an, t, ib, 1 + split_parts(an.compute) + (xv ? 16 : 0) + (yv ? 32 : 0), info);
-  if (offs) {
-    const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N + 3 * an.L;
-    if (offs_len < need) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: offsets buffer too short");
-    if (an.M == 0 || an.N == 0) all_offsets(an, v);
-    int64_t pos = 0;
-    for (int i = 0; i < 9; ++i) {
-      std::copy(v[i].begin(), v[i].end(), offs + pos);
-      pos += (int64_t)v[i].size();
-    }
-  }
-  return FAMLIES_OK;
-}
-
-famlies_status famlies_plan_contract(famlies_handle h, famlies_plan* out, int dtype, int compute,
+famlies_status famlies_plan_contract(famlies_handle htok, famlies_plan* out, int dtype, int compute,
                                      const famlies_tensor* A, const famlies_tensor* B,
                                      const famlies_tensor* C) {
-  return make_plan(h, out, dtype, compute, A, B, C, nullptr);
-}
-
-famlies_status famlies_plan_destroy(famlies_plan p) {
-  if (!p || !is_live(p)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_destroy: invalid plan");
-  unregister_live(p);
-  DeviceGuard dg(p->h->device);
-  delete p;
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
+  *out = nullptr;
+  famlies_plan_s* p = nullptr;
+  famlies_status st = no_throw("famlies_plan_contract",
+                               [&] { return make_plan(handle_of(htok), &p, dtype, compute, A, B, C, nullptr); });
+  if (st != FAMLIES_OK) return st;
+  void* tok = registry_add(p, ObjKind::kPlan);
+  if (!tok) {
+    destroy_plan(p);
+    return fail(FAMLIES_ERR_ALLOC, "famlies_plan_contract: no free object slot");
+  }
+  *out = static_cast<famlies_plan>(tok);
   return FAMLIES_OK;
 }
 
-famlies_status famlies_plan_get_info(famlies_plan p, famlies_plan_info* info) {
-  if (!p || !is_live(p) || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
+famlies_status famlies_plan_destroy(famlies_plan tok) {
+  auto* p = static_cast<famlies_plan_s*>(registry_take(tok, ObjKind::kPlan));
+  if (!p) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_destroy: invalid plan");
+  destroy_plan(p);
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_plan_get_info(famlies_plan tok, famlies_plan_info* info) {
+  famlies_plan_s* p = plan_of(tok);
+  if (!p || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
   fill_info(p->an, p->cfg, p->index_bits,
             1 + split_parts(p->an.compute) + (p->x_vec ? 16 : 0) + (p->y_vec ? 32 : 0), info);
   return FAMLIES_OK;
@@ -521,9 +325,13 @@ static bool overlaps(const void* p, int64_t plo, int64_t phi, const void* q, int
   return a0 < b1 && b0 < a1;
 }
 
-static famlies_status execute_impl(famlies_plan p, double alpha, const void* A, const void* B, double beta,
-                                   void* C, int packed, void* stream) {
-  if (!p || !is_live(p) || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute: invalid plan");
+}  // extern "C"
+
+namespace famlies {
+
+famlies_status execute_impl(famlies_plan_s* p, double alpha, const void* A, const void* B, double beta,
+                            void* C, int packed, void* stream) {
+  if (!p || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute: invalid plan");
   const Analysis& an = p->an;
   if (an.M == 0 || an.N == 0) return FAMLIES_OK;
   const bool need_ab = alpha != 0.0 && an.K > 0;
@@ -534,12 +342,12 @@ static famlies_status execute_impl(famlies_plan p, double alpha, const void* A, 
   const bool pa = packed & 1, pb = packed & 2;
   size_t sza = 0, szb = 0;
   if (need_ab && pa) {
-    famlies_status st = famlies_pack_size(p, 0, &sza);
+    famlies_status st = pack_size_impl(p, 0, &sza);
     if (st != FAMLIES_OK) return st;
     if ((uintptr_t)A & 15) return fail(FAMLIES_ERR_ALIGN, "famlies_execute_packed: packed A not 16-byte aligned");
   }
   if (need_ab && pb) {
-    famlies_status st = famlies_pack_size(p, 1, &szb);
+    famlies_status st = pack_size_impl(p, 1, &szb);
     if (st != FAMLIES_OK) return st;
     if ((uintptr_t)B & 15) return fail(FAMLIES_ERR_ALIGN, "famlies_execute_packed: packed B not 16-byte aligned");
   }
@@ -599,15 +407,19 @@ static famlies_status execute_impl(famlies_plan p, double alpha, const void* A, 
   return FAMLIES_OK;
 }
 
-famlies_status famlies_execute(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+}  // namespace famlies
+
+extern "C" {
+
+famlies_status famlies_execute(famlies_plan tok, double alpha, const void* A, const void* B, double beta,
                                void* C, void* stream) {
-  return execute_impl(p, alpha, A, B, beta, C, 0, stream);
+  return execute_impl(plan_of(tok), alpha, A, B, beta, C, 0, stream);
 }
 
-famlies_status famlies_execute_packed(famlies_plan p, double alpha, const void* A, const void* B, double beta,
+famlies_status famlies_execute_packed(famlies_plan tok, double alpha, const void* A, const void* B, double beta,
                                       void* C, int packed, void* stream) {
   if (packed < 0 || packed > 3) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute_packed: packed must be 0..3");
-  return execute_impl(p, alpha, A, B, beta, C, packed, stream);
+  return execute_impl(plan_of(tok), alpha, A, B, beta, C, packed, stream);
 }
 
 }  // extern "C"

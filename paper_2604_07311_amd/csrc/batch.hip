@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -182,11 +183,12 @@ using namespace famlies;
 
 extern "C" {
 
-famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype, int64_t n,
-                                  const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
+static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
+                                      const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
   if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: null output pointer");
   *out = nullptr;
-  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: invalid handle");
+  famlies_handle_s* h = handle_of(htok);
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: invalid handle");
   if (n < 0 || (n > 0 && (!A || !B || !C))) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: bad arrays");
   if (n > (1 << 30)) return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: too many problems");
   auto* bp = new (std::nothrow) BatchPlan();
@@ -241,10 +243,22 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
     const int64_t len[6] = {an.M, an.K, an.K, an.N, an.M, an.N};
     const int64_t padded[6] = {mp, kp, kp, np, mp, np};
     const int64_t shift[6] = {an.x_lo, 0, 0, an.y_lo, an.c_lo_mn, 0};
+    std::vector<int64_t> vecs[6];
     for (int v = 0; v < 6; ++v) {
       d.pos[v] = (int32_t)(pool.size() - d.off);
-      offsets(*groups[v], which[v], len[v], padded[v], tmp);
-      for (int64_t x : tmp) pool.push_back((uint32_t)(uint64_t)((x - shift[v]) * es));  // byte offsets, mod 2^32
+      offsets(*groups[v], which[v], len[v], padded[v], vecs[v]);
+      for (int64_t x : vecs[v]) pool.push_back((uint32_t)(uint64_t)((x - shift[v]) * es));  // byte offsets, mod 2^32
+    }
+    // host-side bounds check of the vectors against the descriptors' spans
+    const std::vector<int64_t> zero(1, 0);
+    const int64_t x_lo = an.swapped ? an.b_lo : an.a_lo, x_hi = an.swapped ? an.b_hi : an.a_hi;
+    const int64_t y_lo = an.swapped ? an.a_lo : an.b_lo, y_hi = an.swapped ? an.a_hi : an.b_hi;
+    if ((an.K > 0 && (!offsets_in_span(vecs[0], an.M, vecs[1], an.K, zero, 1, x_lo, x_hi) ||
+                      !offsets_in_span(vecs[3], an.N, vecs[2], an.K, zero, 1, y_lo, y_hi))) ||
+        !offsets_in_span(vecs[4], an.M, vecs[5], an.N, zero, 1, an.c_lo, an.c_hi)) {
+      delete bp;
+      return fail(FAMLIES_ERR_BOUNDS, "problem " + std::to_string(p) +
+                                          ": an indexing vector addresses outside its tensor's span");
     }
     if (an.K == 0) {
       bp->scale_only.push_back((int)p);
@@ -358,14 +372,28 @@ famlies_status famlies_batch_plan(famlies_handle h, famlies_plan* out, int dtype
   p->an.dtype = dtype;
   p->an.esize = dtype == FAMLIES_F64 ? 8 : 4;
   p->batch = bp;
-  register_live(p);
-  *out = p;
+  if (log_enabled())
+    std::fprintf(stderr, "[famlies] batch plan %s: %lld problems, %lld (problem, tile) items, grid %d, %zu K = 0\n",
+                 dtype == FAMLIES_F64 ? "f64" : "f32", (long long)n, (long long)bp->n_items, bp->grid,
+                 bp->scale_only.size());
+  void* tok = registry_add(p, ObjKind::kPlan);
+  if (!tok) {
+    destroy_plan(p);
+    return fail(FAMLIES_ERR_ALLOC, "famlies_batch_plan: no free object slot");
+  }
+  *out = static_cast<famlies_plan>(tok);
   return FAMLIES_OK;
 }
 
-famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta, const void* const* A_dev,
+famlies_status famlies_batch_plan(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
+                                  const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
+  return no_throw("famlies_batch_plan", [&] { return batch_plan_impl(htok, out, dtype, n, A, B, C); });
+}
+
+famlies_status famlies_batch_execute(famlies_plan tok, double alpha, double beta, const void* const* A_dev,
                                      const void* const* B_dev, void* const* C_dev, void* stream) {
-  if (!p || !is_live(p) || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: not a batched plan");
+  famlies_plan_s* p = plan_of(tok);
+  if (!p || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: not a batched plan");
   BatchPlan* bp = p->batch;
   if (bp->n == 0) return FAMLIES_OK;
   if (!A_dev || !B_dev || !C_dev) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: null pointer array");

@@ -76,6 +76,13 @@ struct TileCfg {
   int tail = 0;
 };
 
+// Host-side bounds check of indexing vectors: every address an operand's
+// kernel view forms from the first na, nb, nl entries of a, b and l
+// (a[i] + b[j] + l[k], element offsets) lies in [lo, hi].  The vectors are
+// separable, so the extreme addresses are sums of each vector's extremes.
+bool offsets_in_span(const std::vector<int64_t>& a, int64_t na, const std::vector<int64_t>& b, int64_t nb,
+                     const std::vector<int64_t>& l, int64_t nl, int64_t lo, int64_t hi);
+
 void set_error(const std::string& msg);
 
 }  // namespace famlies

@@ -54,7 +54,7 @@ struct famlies_network_s {
   bool compiled = false;
   ~famlies_network_s() {
     for (auto& s : steps) {
-      if (s.plan) (void)famlies_plan_destroy(s.plan);
+      if (s.plan) famlies::destroy_plan(s.plan);
       for (void* q : s.packed)
         if (q) (void)hipFree(q);
     }
@@ -65,12 +65,17 @@ struct famlies_network_s {
 
 using namespace famlies;
 
+static famlies_network_s* network_of(const void* tok) {
+  return static_cast<famlies_network_s*>(registry_get(tok, ObjKind::kNetwork));
+}
+
 extern "C" {
 
-famlies_status famlies_network_create(famlies_handle h, famlies_network* out, int dtype, int compute) {
+famlies_status famlies_network_create(famlies_handle htok, famlies_network* out, int dtype, int compute) {
   if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_create: null output");
   *out = nullptr;
-  if (!h || !is_live(h)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_create: invalid handle");
+  famlies_handle_s* h = handle_of(htok);
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_create: invalid handle");
   if (dtype != FAMLIES_F64 && dtype != FAMLIES_F32) return fail(FAMLIES_ERR_INVALID_ARG, "bad dtype");
   if (compute < FAMLIES_NATIVE || compute > FAMLIES_BF16X6 || (compute != FAMLIES_NATIVE && dtype != FAMLIES_F32))
     return fail(FAMLIES_ERR_INVALID_ARG, "bad compute mode for this dtype");
@@ -79,22 +84,27 @@ famlies_status famlies_network_create(famlies_handle h, famlies_network* out, in
   n->h = h;
   n->dtype = dtype;
   n->compute = compute;
-  register_live(n);
-  *out = n;
+  void* tok = registry_add(n, ObjKind::kNetwork);
+  if (!tok) {
+    delete n;
+    return fail(FAMLIES_ERR_ALLOC, "famlies_network_create: no free object slot");
+  }
+  *out = static_cast<famlies_network>(tok);
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_destroy(famlies_network n) {
-  if (!n || !is_live(n)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_destroy: invalid network");
-  unregister_live(n);
+famlies_status famlies_network_destroy(famlies_network tok) {
+  auto* n = static_cast<famlies_network_s*>(registry_take(tok, ObjKind::kNetwork));
+  if (!n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_destroy: invalid network");
   DeviceGuard dg(n->h->device);
   delete n;
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_add_tensor(famlies_network n, const famlies_tensor* desc, int intermediate,
-                                          int32_t* id) {
-  if (!n || !is_live(n) || !desc || !id) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_tensor: bad argument");
+static famlies_status add_tensor_impl(famlies_network tok, const famlies_tensor* desc, int intermediate,
+                                      int32_t* id) {
+  famlies_network_s* n = network_of(tok);
+  if (!n || !desc || !id) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_tensor: bad argument");
   if (n->compiled) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_tensor: network already compiled");
   if (desc->rank < 0 || desc->rank > FAMLIES_MAX_RANK || (desc->rank > 0 && (!desc->extents || !desc->strides || !desc->labels)))
     return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_tensor: bad descriptor");
@@ -112,14 +122,21 @@ famlies_status famlies_network_add_tensor(famlies_network n, const famlies_tenso
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_add_contraction(famlies_network n, double alpha, int32_t a, int32_t b, double beta,
+famlies_status famlies_network_add_tensor(famlies_network tok, const famlies_tensor* desc, int intermediate,
+                                          int32_t* id) {
+  return no_throw("famlies_network_add_tensor", [&] { return add_tensor_impl(tok, desc, intermediate, id); });
+}
+
+famlies_status famlies_network_add_contraction(famlies_network tok, double alpha, int32_t a, int32_t b, double beta,
                                                int32_t c, int flags) {
-  if (!n || !is_live(n)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_contraction: invalid network");
+  famlies_network_s* n = network_of(tok);
+  if (!n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_contraction: invalid network");
   if (n->compiled) return fail(FAMLIES_ERR_INVALID_ARG, "network already compiled");
   const int32_t nt = (int32_t)n->tensors.size();
   if (a < 0 || a >= nt || b < 0 || b >= nt || c < 0 || c >= nt)
     return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_add_contraction: tensor id out of range");
   if (c == a || c == b) return fail(FAMLIES_ERR_ALIAS, "famlies_network_add_contraction: C is also an input");
+  if (n->steps.size() >= (size_t)1 << 20) return fail(FAMLIES_ERR_UNSUPPORTED, "too many network steps");
   NetStep s;
   s.alpha = alpha;
   s.beta = beta;
@@ -128,12 +145,15 @@ famlies_status famlies_network_add_contraction(famlies_network n, double alpha, 
   s.c = c;
   s.pack_a = flags & FAMLIES_NET_PACK_A;
   s.pack_b = flags & FAMLIES_NET_PACK_B;
-  n->steps.push_back(s);
-  return FAMLIES_OK;
+  return no_throw("famlies_network_add_contraction", [&] {
+    n->steps.push_back(s);
+    return FAMLIES_OK;
+  });
 }
 
-famlies_status famlies_network_compile(famlies_network n) {
-  if (!n || !is_live(n)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_compile: invalid network");
+static famlies_status compile_impl(famlies_network tok) {
+  famlies_network_s* n = network_of(tok);
+  if (!n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_compile: invalid network");
   if (n->compiled) return FAMLIES_OK;
   DeviceGuard dg(n->h->device);
   if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the network's device");
@@ -164,7 +184,7 @@ famlies_status famlies_network_compile(famlies_network n) {
     for (int op = 0; op < 2; ++op) {
       if (!(op == 0 ? s.pack_a : s.pack_b)) continue;
       size_t bytes = 0;
-      st = famlies_pack_size(s.plan, op, &bytes);
+      st = pack_size_impl(s.plan, op, &bytes);
       if (st == FAMLIES_ERR_UNSUPPORTED) {  // this plan has no packed kernel: gather instead
         (op == 0 ? s.pack_a : s.pack_b) = false;
         continue;
@@ -178,8 +198,13 @@ famlies_status famlies_network_compile(famlies_network n) {
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_bind(famlies_network n, int32_t id, void* ptr) {
-  if (!n || !is_live(n)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_bind: invalid network");
+famlies_status famlies_network_compile(famlies_network tok) {
+  return no_throw("famlies_network_compile", [&] { return compile_impl(tok); });
+}
+
+famlies_status famlies_network_bind(famlies_network tok, int32_t id, void* ptr) {
+  famlies_network_s* n = network_of(tok);
+  if (!n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_bind: invalid network");
   if (id < 0 || id >= (int32_t)n->tensors.size()) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_bind: bad id");
   NetTensor& t = n->tensors[(size_t)id];
   if (t.intermediate) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_bind: tensor is an intermediate");
@@ -188,15 +213,17 @@ famlies_status famlies_network_bind(famlies_network n, int32_t id, void* ptr) {
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_tensor_ptr(famlies_network n, int32_t id, void** ptr) {
-  if (!n || !is_live(n) || !ptr) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_tensor_ptr: bad argument");
+famlies_status famlies_network_tensor_ptr(famlies_network tok, int32_t id, void** ptr) {
+  famlies_network_s* n = network_of(tok);
+  if (!n || !ptr) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_tensor_ptr: bad argument");
   if (id < 0 || id >= (int32_t)n->tensors.size()) return fail(FAMLIES_ERR_INVALID_ARG, "bad tensor id");
   *ptr = n->tensors[(size_t)id].ptr;
   return FAMLIES_OK;
 }
 
-famlies_status famlies_network_execute(famlies_network n, void* stream) {
-  if (!n || !is_live(n)) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_execute: invalid network");
+famlies_status famlies_network_execute(famlies_network tok, void* stream) {
+  famlies_network_s* n = network_of(tok);
+  if (!n) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_execute: invalid network");
   if (!n->compiled) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_execute: compile the network first");
   for (const auto& t : n->tensors)
     if (!t.intermediate && !t.ptr) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_network_execute: unbound tensor");
@@ -214,14 +241,14 @@ famlies_status famlies_network_execute(famlies_network n, void* stream) {
       // changes every run, so it is packed every run.
       const uint64_t v = src[op]->intermediate ? 0 : src[op]->version;
       if (src[op]->intermediate || s.packed_version[op] != v) {
-        famlies_status st = famlies_pack(s.plan, op, src[op]->ptr, s.packed[op], stream);
+        famlies_status st = pack_impl(s.plan, op, src[op]->ptr, s.packed[op], stream);
         if (st != FAMLIES_OK) return st;
         s.packed_version[op] = v;
       }
       (op == 0 ? A : B) = s.packed[op];
       mask |= 1 << op;
     }
-    famlies_status st = famlies_execute_packed(s.plan, s.alpha, A, B, s.beta, tc.ptr, mask, stream);
+    famlies_status st = execute_impl(s.plan, s.alpha, A, B, s.beta, tc.ptr, mask, stream);
     if (st != FAMLIES_OK) return st;
   }
   return FAMLIES_OK;

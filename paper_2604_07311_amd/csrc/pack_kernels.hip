@@ -120,8 +120,8 @@ struct PackGeom {
   size_t bytes;
 };
 
-famlies_status pack_geom(famlies_plan p, int operand, PackGeom* g) {
-  if (!p || !is_live(p) || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "pack: invalid plan");
+famlies_status pack_geom(famlies_plan_s* p, int operand, PackGeom* g) {
+  if (!p || p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "pack: invalid plan");
   if (operand != 0 && operand != 1) return fail(FAMLIES_ERR_INVALID_ARG, "pack: operand must be 0 (A) or 1 (B)");
   const Analysis& an = p->an;
   const int ns = split_parts(an.compute);
@@ -143,9 +143,9 @@ famlies_status pack_geom(famlies_plan p, int operand, PackGeom* g) {
 
 }  // namespace
 
-extern "C" {
+namespace famlies {
 
-famlies_status famlies_pack_size(famlies_plan p, int operand, size_t* bytes) {
+famlies_status pack_size_impl(famlies_plan_s* p, int operand, size_t* bytes) {
   if (!bytes) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_pack_size: null output");
   PackGeom g;
   famlies_status st = pack_geom(p, operand, &g);
@@ -154,7 +154,7 @@ famlies_status famlies_pack_size(famlies_plan p, int operand, size_t* bytes) {
   return FAMLIES_OK;
 }
 
-famlies_status famlies_pack(famlies_plan p, int operand, const void* src, void* dst, void* stream) {
+famlies_status pack_impl(famlies_plan_s* p, int operand, const void* src, void* dst, void* stream) {
   PackGeom g;
   famlies_status st = pack_geom(p, operand, &g);
   if (st != FAMLIES_OK) return st;
@@ -182,6 +182,18 @@ famlies_status famlies_pack(famlies_plan p, int operand, const void* src, void* 
   hipError_t e = launch_pack(a, an.dtype, split_parts(an.compute), g.br, g.bk, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
   return FAMLIES_OK;
+}
+
+}  // namespace famlies
+
+extern "C" {
+
+famlies_status famlies_pack_size(famlies_plan tok, int operand, size_t* bytes) {
+  return pack_size_impl(plan_of(tok), operand, bytes);
+}
+
+famlies_status famlies_pack(famlies_plan tok, int operand, const void* src, void* dst, void* stream) {
+  return pack_impl(plan_of(tok), operand, src, dst, stream);
 }
 
 }  // extern "C"

@@ -380,4 +380,23 @@ void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad
   }
 }
 
+bool offsets_in_span(const std::vector<int64_t>& a, int64_t na, const std::vector<int64_t>& b, int64_t nb,
+                     const std::vector<int64_t>& l, int64_t nl, int64_t lo, int64_t hi) {
+  if (na <= 0 || nb <= 0 || nl <= 0) return true;  // no element is addressed
+  if ((int64_t)a.size() < na || (int64_t)b.size() < nb || (int64_t)l.size() < nl || lo > hi) return false;
+  auto ext = [](const std::vector<int64_t>& v, int64_t n, int64_t* mn, int64_t* mx) {
+    *mn = *mx = v[0];
+    for (int64_t i = 1; i < n; ++i) {
+      *mn = std::min(*mn, v[(size_t)i]);
+      *mx = std::max(*mx, v[(size_t)i]);
+    }
+  };
+  int64_t a0, a1, b0, b1, l0, l1;
+  ext(a, na, &a0, &a1);
+  ext(b, nb, &b0, &b1);
+  ext(l, nl, &l0, &l1);
+  // |offsets| are bounded by the spans checked in analyze(), far below 2^62
+  return a0 + b0 + l0 >= lo && a1 + b1 + l1 <= hi;
+}
+
 }  // namespace famlies

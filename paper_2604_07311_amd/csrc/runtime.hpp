@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -57,6 +59,7 @@ struct famlies_plan_s {
   // X / Y are K-gathered from affine unit-stride K blocks with 16-byte
   // aligned run starts (given a 16-byte aligned base pointer)
   bool x_vec = false, y_vec = false;
+  bool table_hit = false;  // the tile came from the handle's tile table
   void* d_work = nullptr;  // split-K partial sums
   size_t work_bytes = 0;
   famlies::BatchPlan* batch = nullptr;  // set for batched plans
@@ -74,10 +77,71 @@ struct DeviceGuard {
 
 famlies_status fail(famlies_status st, const std::string& msg);
 famlies_status hip_fail(hipError_t e, const char* what);
-void register_live(const void* p);
-void unregister_live(const void* p);
-bool is_live(const void* p);
-TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an);
+
+// Runs f() so that nothing throws across the C ABI: a host allocation
+// failure becomes FAMLIES_ERR_ALLOC, any other C++ exception
+// FAMLIES_ERR_INVALID_ARG.
+template <typename F>
+famlies_status no_throw(const char* where, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(FAMLIES_ERR_ALLOC, std::string(where) + ": out of host memory");
+  } catch (const std::exception& e) {
+    return fail(FAMLIES_ERR_INVALID_ARG, std::string(where) + ": " + e.what());
+  }
+}
+
+// GEMM dimensions the single-contraction kernels index with 32-bit ints.
+constexpr int64_t kMaxGemmDim = ((int64_t)1 << 31) - 1024;
+
+// The opaque pointers of the C ABI are generation-counted tokens (see
+// registry.cpp): registry_add returns the token for a new object (null when
+// out of slots), registry_get resolves a token of kind k (null when it is
+// unknown, retired or of another kind), registry_take resolves it and
+// retires it.
+enum class ObjKind : uint32_t { kHandle = 1, kPlan = 2, kNetwork = 3 };
+void* registry_add(void* obj, ObjKind k);
+void* registry_get(const void* tok, ObjKind k);
+void* registry_take(const void* tok, ObjKind k);
+inline famlies_handle_s* handle_of(const void* tok) {
+  return static_cast<famlies_handle_s*>(registry_get(tok, ObjKind::kHandle));
+}
+inline famlies_plan_s* plan_of(const void* tok) {
+  return static_cast<famlies_plan_s*>(registry_get(tok, ObjKind::kPlan));
+}
+
+// Plan decisions are written to stderr when the environment variable
+// FAMLIES_LOG is set to a non-empty value other than "0".
+bool log_enabled();
+void log_plan(const famlies_plan_s* p);
+void log_decision(const char* what, const Analysis& an, const TileCfg& cfg, int index_bits, bool x_vec,
+                  bool y_vec, size_t work_bytes, bool table_hit);
+
+// Internal forms of the ABI calls, on resolved objects.
+famlies_status execute_impl(famlies_plan_s* p, double alpha, const void* A, const void* B, double beta,
+                            void* C, int packed, void* stream);
+famlies_status pack_size_impl(famlies_plan_s* p, int operand, size_t* bytes);
+famlies_status pack_impl(famlies_plan_s* p, int operand, const void* src, void* dst, void* stream);
+void destroy_plan(famlies_plan_s* p);
+// from_table (may be null) is set when the handle's tile table decided.
+TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an, bool* from_table = nullptr);
+
+// Host planning helpers (plan_host.cpp).
+int64_t ceil_div(int64_t a, int64_t b);
+// Settle split-K: K slices of whole BK-blocks, and the number of tiles
+// computed whole first (*head; every tile when there is no split).
+void finalize_split(TileCfg* t, int64_t K, int64_t ntiles, int* kchunk, int* head);
+void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int kernel, famlies_plan_info* info);
+// 32: uint32 byte offsets from each operand's lowest element (every operand
+// spans less than 4 GiB over its non-batch modes); 64: int64 element offsets.
+int index_bits_for(const Analysis& an);
+// Affine-block flags of X and Y for a plan with K-slice depth bk; v holds
+// the nine indexing vectors in upload order.
+void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int64_t>* v, bool* xv, bool* yv);
+// The nine indexing vectors, unpadded: X rows, X k, Y k, Y cols, C rows,
+// C cols, batch offsets of X, Y, C.
+void all_offsets(const Analysis& an, std::vector<int64_t>* v);
 // Plan one contraction; `force` (may be null) overrides the tile choice.
 famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, int compute,
                          const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,

@@ -62,8 +62,9 @@ using namespace famlies;
 
 extern "C" {
 
-famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags) {
-  if (!h || !is_live(h) || !table_path) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_tune: invalid argument");
+static famlies_status tune_impl(famlies_handle htok, const char* table_path, int flags) {
+  famlies_handle_s* h = handle_of(htok);
+  if (!h || !table_path) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_tune: invalid argument");
   const bool quick = flags & 1;
   DeviceGuard dg(h->device);
   if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
@@ -125,7 +126,7 @@ famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags)
             const TileCfg eff = p->cfg;  // split after the planner's rounding
             float ms = 0.f;
             st = time_plan(p, buf, s, reps, &ms);
-            (void)famlies_plan_destroy(p);
+            destroy_plan(p);
             if (st != FAMLIES_OK) return st;
             if (ms < best) {
               best = ms;
@@ -158,11 +159,18 @@ famlies_status famlies_tune(famlies_handle h, const char* table_path, int flags)
   return FAMLIES_OK;
 }
 
-famlies_status famlies_load_tune_table(famlies_handle h, const char* table_path) {
-  if (!h || !is_live(h) || !table_path) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_load_tune_table: invalid argument");
-  std::string err;
-  if (!h->table.load(table_path, &err)) return fail(FAMLIES_ERR_INVALID_ARG, err);
-  return FAMLIES_OK;
+famlies_status famlies_tune(famlies_handle htok, const char* table_path, int flags) {
+  return no_throw("famlies_tune", [&] { return tune_impl(htok, table_path, flags); });
+}
+
+famlies_status famlies_load_tune_table(famlies_handle htok, const char* table_path) {
+  famlies_handle_s* h = handle_of(htok);
+  if (!h || !table_path) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_load_tune_table: invalid argument");
+  return no_throw("famlies_load_tune_table", [&] {
+    std::string err;
+    if (!h->table.load(table_path, &err)) return fail(FAMLIES_ERR_INVALID_ARG, err);
+    return FAMLIES_OK;
+  });
 }
 
 }  // extern "C"

@@ -351,3 +351,38 @@ def test_tail_split_choice(fm):
     p16 = synth.plain16(with_data=False)
     info = analyze(p16, fm.FAMLIES_F64)
     assert info["split_k"] > 1 and info["split_tiles"] == (256 // info["tile_m"]) ** 2
+
+
+def test_plan_log(tmp_path):
+    """FAMLIES_LOG=1 writes one line per planning decision to stderr."""
+    import subprocess
+    import sys
+    code = ("import paper_2604_07311_amd as fm, synth\n"
+            "p = synth.ladder(128, 32, with_data=False)\n"
+            "fm.famlies_analyze(fm.FAMLIES_F64, 0, fm.make_desc(p.a.extents, p.a.strides, p.la),\n"
+            "                   fm.make_desc(p.b.extents, p.b.strides, p.lb),\n"
+            "                   fm.make_desc(p.c.extents, p.c.strides, p.lc))\n")
+    env = dict(os.environ, FAMLIES_LOG="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[famlies]")]
+    assert len(lines) == 1, r.stderr
+    assert "analyze f64/native M=1024 N=16384 K=16384" in lines[0] and "tile=128x128x16" in lines[0], lines[0]
+    env["FAMLIES_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert "[famlies]" not in r.stderr
+
+
+def test_bad_tokens_rejected(fm):
+    """Opaque pointers are generation-counted tokens: made-up values, null
+    and pointers of another kind are rejected with INVALID_ARG, not used."""
+    for bad in (0, 1, 0x1234, 0x7fff0000, (5 << 32) | (3 << 4) | 2):
+        with pytest.raises(fm.FamliesError) as e:
+            fm.famlies_plan_destroy(bad)
+        assert e.value.code == fm.FAMLIES_ERR_INVALID_ARG
+        with pytest.raises(fm.FamliesError) as e:
+            fm.famlies_plan_get_info(bad)
+        assert e.value.code == fm.FAMLIES_ERR_INVALID_ARG
+        with pytest.raises(fm.FamliesError) as e:
+            fm.famlies_destroy(bad)
+        assert e.value.code == fm.FAMLIES_ERR_INVALID_ARG
