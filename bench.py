@@ -258,26 +258,21 @@ def cpu_baseline(p, target_s=12.0):
 # HBM bytes per launch of a workload's dominant kernel, from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE: KiB per dispatch), each scaled by
 # the ratio the same counter shows for a plain device copy of 1 GiB taken in
-# the same run.  A record holds only for the kernel sources it was measured
-# on (`sources` = kernel_sources_sha() then); after any change to them the
-# traffic is reported as null until the counters are taken again.
+# the same run.  A record holds only for the kernel it was measured on: the
+# plain kernel's own sources (`sources` = kernel_sources_sha() then) and the
+# plan's launch shape (`plan` = plan_signature() then).  After a change to
+# either the traffic is reported as null until the counters are taken again.
 TRAFFIC = {
     # plain_contract<double,u32,128,128,16,3,3>, ladder v=128 o=32
-    ("ladder", "f64", 128, 32): {"fetch_kib": 3.5734e6, "write_kib": 131072.0, "fetch_scale": 1.9999,
-                                 "write_scale": 1.0, "sources": "2be8e8199d3ad8e5",
-                                 "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, profiles/plain_contract_ladder_v128_o32_write_size.md"},
+    ("ladder", "f64", 128, 32): None,
     # plain_contract<float,u32,128,128,32,3,3>, ladder v=128 o=32
-    ("ladder", "f32", 128, 32): {"fetch_kib": 2.7993e6, "write_kib": 65536.0, "fetch_scale": 1.9999,
-                                 "write_scale": 1.0, "sources": "2be8e8199d3ad8e5",
-                                 "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, profiles/plain_contract_ladder_v128_o32_write_size.md"},
+    ("ladder", "f32", 128, 32): None,
 }
 
 
-# Sources of the plain contraction kernels and their planning (the kernels
-# the traffic records are taken on); the split, batched, packing and network
-# sources do not enter them.
-PLAIN_SOURCES = ("abi.hip", "args.hpp", "device.hpp", "internal.hpp", "launch.hpp", "plain_kernels.hip",
-                 "planner.cpp", "runtime.hpp", "table.cpp", "tile.hpp")
+# Sources of the plain contraction kernels themselves; the planner enters a
+# record through the plan's launch shape instead.
+PLAIN_SOURCES = ("args.hpp", "device.hpp", "launch.hpp", "plain_kernels.hip", "tile.hpp")
 
 
 def kernel_sources_sha():
@@ -291,18 +286,25 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def traffic(key):
+def plan_signature(info):
+    """The launch shape a traffic record depends on."""
+    return "%dx%dx%d split%d/%d kernel%d bits%d" % (info["tile_m"], info["tile_n"], info["tile_k"],
+                                                   info["split_k"], info["split_tiles"], info["kernel"],
+                                                   info["index_bits"])
+
+
+def traffic(key, info):
     rec = TRAFFIC.get(key)
-    if rec is None or rec["sources"] != kernel_sources_sha():
+    if rec is None or rec["sources"] != kernel_sources_sha() or rec["plan"] != plan_signature(info):
         return None
     return int(round(1024 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])))
 
 
-def roofline(flops, launch_ms, peak, bound="mfma", key=None):
+def roofline(flops, launch_ms, peak, bound="mfma", key=None, info=None):
     achieved = flops / (launch_ms * 1e-3) / 1e12
     return {"bound": bound, "achieved": round(achieved, 3), "peak": round(peak / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / peak, 4),
-            "traffic": traffic(key) if key else None}
+            "traffic": traffic(key, info) if key else None}
 
 
 def base_record(args, value, ms, dtype, config, unit="GFLOP/s"):
@@ -354,7 +356,8 @@ def wl_ladder(args):
                        "split_k": r["info"]["split_k"]})
     out["pct_mfma_peak"] = round(100 * flops / (r["ms"] * 1e-3) / PEAK[head], 2)
     out["error_vs_fp64"] = r["check"]
-    out["roofline"] = roofline(flops, r["launch"], PEAK[head], key=("ladder", head, args.v, args.o))
+    out["roofline"] = roofline(flops, r["launch"], PEAK[head], key=("ladder", head, args.v, args.o),
+                               info=r["info"])
     if "packed_W" in r:
         out["packed_W"] = r["packed_W"]
     if "context_torch" in r:
@@ -366,15 +369,50 @@ def wl_ladder(args):
         out.setdefault("secondary", {})[dt] = {
             "value": round(v / 1e9, 2), "unit": "GFLOP/s", "ms_per_step": round(rr["ms"], 4),
             "pct_mfma_peak": round(100 * v / PEAK[dt], 2), "error_vs_fp64": rr["check"],
-            "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt], key=("ladder", dt, args.v, args.o))}
+            "roofline": roofline(rr["info"]["flops"], rr["launch"], PEAK[dt], key=("ladder", dt, args.v, args.o),
+                                 info=rr["info"])}
         if "packed_W" in rr:
             out["secondary"][dt]["packed_W"] = rr["packed_W"]
         if "context_torch" in rr:
             out["secondary"][dt]["context_torch"] = rr["context_torch"]
+    if not args.no_ring:
+        out.setdefault("secondary", {})["ring_o48_v192"] = ring_precisions(args)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(probs[head])
     return out
+
+
+def ring_precisions(args):
+    """The split-BF16 precision path beside plain FP32 and FP64 on one
+    workload: the ring C[a,i,b,j] = sum_{k,c} X[a,k,i,c] Y[c,b,k,j], o=48,
+    v=192, FP32 inputs N(0,1) with Bernoulli(1e-3) x 1e4 outliers.  Each
+    precision: FP32-equivalent GFLOP/s (2MNK/t), error against the FP64
+    oracle on sampled entries, speed-up over FP32, and a roofline against
+    its own MFMA peak on the flops it issues (bf16x3: 3 * 2MNK, bf16x6:
+    6 * 2MNK on BF16 MFMA)."""
+    import synth
+    log("ring o=48 v=192 with outliers: generating")
+    p = synth.ring(48, 192, seed=4, dist="outliers", dtype=np.float32)
+    res = {}
+    for dtype, comp, issued, peak in (("f32", "native", 1, "f32"), ("f32", "bf16x3", 3, "bf16"),
+                                      ("f32", "bf16x6", 6, "bf16"), ("f64", "native", 1, "f64")):
+        s = Single(p, dtype, comp)
+        check = sample_check(p, s.result_once(), dtype, n=1024)
+        ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
+        flops = s.info["flops"]
+        name = "fp64" if dtype == "f64" else ("fp32" if comp == "native" else comp)
+        res[name] = {"value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s (2MNK/t)",
+                     "ms_per_step": round(ms, 4), "error_vs_fp64": check,
+                     "tile": [s.info["tile_m"], s.info["tile_n"], s.info["tile_k"]],
+                     "split_k": s.info["split_k"], "kernel": s.info["kernel"],
+                     "roofline": roofline(issued * flops, launch, PEAK[peak])}
+        log("ring %s %s: %.3f ms (%.1f GFLOP/s) check %s" % (dtype, comp, ms, flops / ms / 1e6, check))
+        s.close()
+    for name in ("bf16x3", "bf16x6", "fp64"):
+        res[name]["speedup_vs_fp32"] = round(res["fp32"]["ms_per_step"] / res[name]["ms_per_step"], 3)
+    res["workload"] = "ccsd_ring_o48_v192_outliers"
+    return res
 
 
 def _fp32_vs_bf16x3(args, p, name):
@@ -648,6 +686,8 @@ def main():
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ring", action="store_true",
+                    help="ladder: skip the ring in FP32, bf16x3, bf16x6 and FP64 reported under 'secondary'")
     ap.add_argument("--pack", action="store_true",
                     help="also time the pre-packed path (ladder: W packed once; ring: both operands)")
     ap.add_argument("--context", action="store_true",

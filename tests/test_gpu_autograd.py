@@ -107,3 +107,43 @@ def test_finite_differences_fp64():
             Bm[idx] -= 1.0
             fd = (loss(A, Bp) - loss(A, Bm)).item() / 2.0
             assert abs(fd - B.grad[idx].item()) <= tol
+
+
+@pytest.mark.parametrize("la,lb,lc", [
+    ("aeei", "ebj", "abij"),    # A diagonal over a contracted label
+    ("aaei", "ebj", "aij"),     # A diagonal over a row label
+    ("aeit", "ebj", "abij"),    # t summed inside A
+    ("aei", "ebjs", "abij"),    # s summed inside B
+    ("ttei", "eb", "bi"),       # t repeated and summed inside A
+    ("aei", "ebi", "abi"),      # i in all three (batch)
+])
+def test_gradcheck_general_labels(la, lb, lc):
+    """Diagonal, summed-inside and batch labels: the backward writes the
+    gradient into the diagonal view of a zero-filled tensor, or broadcasts it
+    along a label the other operand and C do not hold (FP64 gradcheck)."""
+    import torch
+    import paper_2604_07311_amd as fm
+    ext = {"a": 3, "b": 2, "e": 3, "i": 2, "j": 2, "t": 3, "s": 2}
+    g = torch.Generator().manual_seed(95)
+    A = torch.rand([ext[c] for c in la], generator=g, dtype=torch.float64).cuda().requires_grad_()
+    B = torch.rand([ext[c] for c in lb], generator=g, dtype=torch.float64).cuda().requires_grad_()
+    f = lambda a, b: fm.contract_ad(1.3, a, la, b, lb, 0.0, None, lc)
+    assert torch.autograd.gradcheck(f, (A, B), eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
+def test_dc0_beta_zero_and_layout():
+    """dC0 = beta * G in C0's own layout (here a transposed view), and zeros
+    when beta = 0 (C0 not read)."""
+    import torch
+    import paper_2604_07311_amd as fm
+    g = torch.Generator().manual_seed(96)
+    A = torch.rand(4, 5, generator=g, dtype=torch.float64).cuda()
+    B = torch.rand(5, 3, generator=g, dtype=torch.float64).cuda()
+    G = torch.randn(4, 3, generator=g, dtype=torch.float64).cuda()
+    for beta in (0.75, 0.0):
+        C0 = torch.rand(3, 4, generator=g, dtype=torch.float64).cuda().t().requires_grad_()
+        C = fm.contract_ad(1.0, A, "ik", B, "kj", beta, C0, "ij")
+        C.backward(G)
+        torch.cuda.synchronize()
+        want = (G * beta).cpu().numpy()
+        np.testing.assert_array_equal(C0.grad.cpu().numpy(), want)

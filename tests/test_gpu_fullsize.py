@@ -1,15 +1,49 @@
 """Parity at the full sizes the benchmark times, in the same launch
 configuration (the default handle's plan): sampled C entries against the
 oracle computed one by one (FP64, compensated), with the same bounds as the
-small-problem tests.  Workloads: the FP64/FP32 ladder v=128 o=32, the ring
-o=48 v=192 in FP32, bf16x3 and bf16x6, the ladder v=192 o=48 whose operands
-span more than 4 GiB (64-bit indexing), and the 20,000-problem batch."""
+small-problem tests.  Workloads: the ladder v=128 o=32 in FP64, FP32 and
+bf16x3; the ring o=48 v=192 in FP32, bf16x3, bf16x6 and FP64 (the FP32 data,
+exact in FP64); the ladder v=192 o=48, whose operands span more than 4 GiB
+(64-bit indexing), in FP32, bf16x3, bf16x6 and FP64; and the 20,000-problem
+batch."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
 from tests.famlies_testutil import U32, U64, gamma
+
+_CACHE = {}
+
+
+def _problem(name):
+    """Each full-size input is generated once per test session."""
+    if name not in _CACHE:
+        _CACHE.clear()  # keep one large problem in host memory at a time
+        if name == "ladder128_f64":
+            _CACHE[name] = synth.ladder(128, 32, seed=2, dtype=np.float64)
+        elif name == "ladder128_f32":
+            _CACHE[name] = synth.ladder(128, 32, seed=2, dtype=np.float32)
+        elif name == "ring":
+            _CACHE[name] = synth.ring(48, 192, seed=4, dtype=np.float32)
+        elif name == "ladder192":
+            _CACHE[name] = synth.ladder(192, 48, seed=3, dist="outliers", dtype=np.float32)
+    return _CACHE[name]
+
+
+def _check(compute, dtype, K, g, want, d, dp):
+    """The bound of each path (the same as the small-problem tests)."""
+    err = np.abs(g - want)
+    if dtype == "f64":
+        assert np.linalg.norm(g - want) <= 1e-12 * np.linalg.norm(want)
+        assert np.all(err <= gamma(K + 2, U64) * d)
+    elif compute == "native":
+        assert np.all(err <= gamma(K + 4, U32) * d)
+    elif compute == "bf16x3":
+        assert np.all(err <= (3.0 * 2.0 ** -16 * (1 + 2.0 ** -8) + gamma(K, 2.0 ** -23) * (1 + 2.0 ** -7)) * dp
+                      + 2.0 ** -23 * d)
+    else:
+        assert np.all(err <= (2.0 ** -22 + gamma(3 * K, 2.0 ** -23) * (1 + 2.0 ** -7)) * dp + 2.0 ** -23 * d)
 
 pytestmark = pytest.mark.gpu
 
@@ -59,54 +93,43 @@ def _sampled(p, got, n, seed, split=0):
     return want, d, dp, got[offs]
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_ladder_v128_o32(dtype):
-    p = synth.ladder(128, 32, seed=2, dtype=np.float64 if dtype == "f64" else np.float32)
-    info, got = _run_single(p, dtype)
-    note("ladder v128 o32 %s: tile %d split %d kernel %d bits %d" % (
-        dtype, info["tile_m"], info["split_k"], info["kernel"], info["index_bits"]))
-    want, d, _, g = _sampled(p, got, 4096, 501)
-    K = 128 * 128
-    if dtype == "f64":
-        assert np.linalg.norm(g - want) <= 1e-12 * np.linalg.norm(want)
-        assert np.all(np.abs(g - want) <= gamma(K + 2, U64) * d)
-    else:
-        assert np.all(np.abs(g - want) <= gamma(K + 4, U32) * d)
+@pytest.mark.parametrize("dtype,compute", [("f64", "native"), ("f32", "native"), ("f32", "bf16x3")])
+def test_ladder_v128_o32(dtype, compute):
+    p = _problem("ladder128_" + dtype)
+    info, got = _run_single(p, dtype, compute)
+    note("ladder v128 o32 %s %s: tile %dx%d split %d kernel %d bits %d" % (
+        dtype, compute, info["tile_m"], info["tile_n"], info["split_k"], info["kernel"], info["index_bits"]))
+    want, d, dp, g = _sampled(p, got, 4096, 501)
+    _check(compute, dtype, 128 * 128, g, want, d, dp)
+    note("ladder v128 o32 %s %s normwise %.3e" % (dtype, compute,
+                                                  np.linalg.norm(g - want) / np.linalg.norm(want)))
 
 
-@pytest.mark.parametrize("compute", ["native", "bf16x3", "bf16x6"])
-def test_ring_o48_v192(compute):
-    p = synth.ring(48, 192, seed=4, dtype=np.float32)
-    info, got = _run_single(p, "f32", compute)
-    note("ring %s: tile %dx%d kernel %d" % (compute, info["tile_m"], info["tile_n"], info["kernel"]))
-    K = 48 * 192
+@pytest.mark.parametrize("dtype,compute", [("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6"),
+                                           ("f64", "native")])
+def test_ring_o48_v192(dtype, compute):
+    p = _problem("ring")
+    info, got = _run_single(p, dtype, compute)
+    note("ring %s %s: tile %dx%d split %d kernel %d" % (dtype, compute, info["tile_m"], info["tile_n"],
+                                                       info["split_k"], info["kernel"]))
     want, d, dp, g = _sampled(p, got, 2048, 502)
-    err = np.abs(g - want)
-    if compute == "native":
-        assert np.all(err <= gamma(K + 4, U32) * d)
-    elif compute == "bf16x3":
-        assert np.all(err <= (3.0 * 2.0 ** -16 * (1 + 2.0 ** -8) + gamma(K, 2.0 ** -23) * (1 + 2.0 ** -7)) * dp
-                      + 2.0 ** -23 * d)
-    else:
-        assert np.all(err <= (2.0 ** -22 + gamma(3 * K, 2.0 ** -23) * (1 + 2.0 ** -7)) * dp + 2.0 ** -23 * d)
-    note("ring %s normwise %.3e" % (compute, np.linalg.norm(g - want) / np.linalg.norm(want)))
+    _check(compute, dtype, 48 * 192, g, want, d, dp)
+    note("ring %s %s normwise %.3e" % (dtype, compute, np.linalg.norm(g - want) / np.linalg.norm(want)))
 
 
-@pytest.mark.parametrize("compute", ["native", "bf16x3"])
-def test_ladder_v192_o48_64bit(compute):
-    """W is 192^4 FP32 elements (5.4 GB): the plan needs 64-bit offsets."""
-    p = synth.ladder(192, 48, seed=3, dist="outliers", dtype=np.float32)
-    info, got = _run_single(p, "f32", compute)
-    note("ladder v192 o48 %s: bits %d kernel %d" % (compute, info["index_bits"], info["kernel"]))
+@pytest.mark.parametrize("dtype,compute", [("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6"),
+                                           ("f64", "native")])
+def test_ladder_v192_o48_64bit(dtype, compute):
+    """W is 192^4 elements (5.4 GB in FP32, 10.9 GB in FP64): the plan needs
+    64-bit offsets."""
+    p = _problem("ladder192")
+    info, got = _run_single(p, dtype, compute)
+    note("ladder v192 o48 %s %s: bits %d kernel %d" % (dtype, compute, info["index_bits"], info["kernel"]))
     assert info["index_bits"] == 64
-    K = 192 * 192
     want, d, dp, g = _sampled(p, got, 1024, 503)
-    err = np.abs(g - want)
-    if compute == "native":
-        assert np.all(err <= gamma(K + 4, U32) * d)
-    else:
-        assert np.all(err <= (3.0 * 2.0 ** -16 * (1 + 2.0 ** -8) + gamma(K, 2.0 ** -23) * (1 + 2.0 ** -7)) * dp
-                      + 2.0 ** -23 * d)
+    _check(compute, dtype, 192 * 192, g, want, d, dp)
+    note("ladder v192 o48 %s %s normwise %.3e" % (dtype, compute,
+                                                  np.linalg.norm(g - want) / np.linalg.norm(want)))
 
 
 def test_batched_20000():
