@@ -32,14 +32,16 @@ from __future__ import annotations
 
 import torch
 
+from . import _labels
 from . import contract as _contract
 
 
 def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first):
     """Gradient with respect to `target` (labels lt): alpha times the
     contraction of G (labels lc) with the other operand (labels lo) onto
-    target's labels, in a tensor laid out like target."""
-    lt = list(lt)
+    target's labels, in a tensor laid out like target.  Labels are taken as
+    integer codes (a string's characters or a sequence of ints)."""
+    lc, lo, lt = _labels(lc), _labels(lo), list(_labels(lt))
     uniq = []
     for ch in lt:
         if ch not in uniq:
