@@ -40,7 +40,7 @@ famlies_status time_plan(famlies_plan_s* p, const Buffers& buf, hipStream_t s, i
   famlies_status st = FAMLIES_OK;
   for (int r = 0; r < reps + 2 && st == FAMLIES_OK; ++r) {
     (void)hipEventRecord(e0, s);
-    st = famlies_execute(p, 1.0, buf.a, buf.b, 0.0, buf.c, s);
+    st = execute_impl(p, 1.0, buf.a, buf.b, 0.0, buf.c, 0, s);
     (void)hipEventRecord(e1, s);
     if (hipEventSynchronize(e1) != hipSuccess) st = fail(FAMLIES_ERR_DEVICE, "hipEventSynchronize");
     float x = 0.f;
