@@ -76,6 +76,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.oracle_bf16_rne.argtypes = [ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(ctypes.c_float), ctypes.c_int64]
     lib.oracle_bf16_rne.restype = None
+    lib.oracle_int8_digits.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int64, ctypes.c_int,
+                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int8)]
+    lib.oracle_int8_digits.restype = None
     _lib_cache[path] = lib
     return lib
 
@@ -133,7 +136,8 @@ def contract(alpha: float,
     """Return a new storage array holding C = alpha*A.B + beta*C0 (C0 = c's
     buffer, which is not modified), and the condition tensor D (same storage
     layout) when ``want_cond``.  ``split``: False / 0 exact products, True / 1
-    the bf16x3 split, 2 the bf16x6 split (see oracle.c)."""
+    the bf16x3 split, 2 the bf16x6 split, int8_slices(s) FP64 emulated on
+    8-bit integer products with s slices (see oracle.c)."""
     lib = lib or load()
     abuf, abase, aext, astr = a
     bbuf, bbase, bext, bstr = b
@@ -180,6 +184,28 @@ def contract_entries(alpha: float, a, la, b, lb, beta: float, c, lc,
     if rc != OK:
         raise OracleError(rc)
     return (out, d) if want_cond else out
+
+
+INT8_BASE = 16
+
+
+def int8_slices(s: int) -> int:
+    """The ``split`` code of FP64 emulated on 8-bit integer products with s
+    slices (1 <= s <= 12; see oracle.c)."""
+    if not 1 <= int(s) <= 12:
+        raise ValueError("slices must be in 1..12")
+    return INT8_BASE + int(s)
+
+
+def int8_digits(x: np.ndarray, e: int, s: int, lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """The s signed 7-bit digits of each x * 2^-e (|x * 2^-e| < 1), shape
+    x.shape + (s,), int8."""
+    lib = lib or load()
+    src = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.zeros(src.size * int(s), dtype=np.int8)
+    lib.oracle_int8_digits(src.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), src.size, int(e), int(s),
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return out.reshape(np.shape(x) + (int(s),))
 
 
 def bf16_rne(x: np.ndarray, lib: Optional[ctypes.CDLL] = None) -> np.ndarray:

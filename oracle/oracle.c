@@ -40,6 +40,23 @@
  *     m = RNE_bf16(x - h), l = RNE_bf16(x - h - m) (the differences are exact
  *     in FP32), and keeps the six products whose orders sum to at most two
  *     units of 2^-8: hh, hm, mh, hl, lh, mm.  Reference for the bf16x6 path.
+ *   - split == 16 + s (1 <= s <= 12) is FP64 emulated on 8-bit integer
+ *     products with s slices (new and mixed precisions, Introduction,
+ *     "Challenges", and "Supporting new and mixed precisions"; the slicing is
+ *     the error-free splitting of Ozaki, Ogita, Oishi and Rump, in the integer
+ *     form of Ootomo, Ozaki and Yokota).  For one C entry the "row" of A is
+ *     every A element its sum reads, and the "column" of B likewise:
+ *       1. each is scaled by a power of two, 2^-ea and 2^-eb, where e is the
+ *          smallest integer with max|v| < 2^e (0 for an all-zero row), so
+ *          every scaled value lies in (-1, 1);
+ *       2. each scaled value v is cut into s signed 7-bit digits, exactly:
+ *          r_0 = v, d_t = trunc(2^7 r_{t-1}), r_t = 2^7 r_{t-1} - d_t, so
+ *          v = sum_t d_t 2^-7t + 2^-7s r_s with |d_t| <= 127, |r_s| < 1;
+ *       3. for every digit pair (t, u) with t + u <= s + 1 the digit products
+ *          are summed over the sum's index space as exact integers S_tu;
+ *       4. the entry's product term is 2^(ea+eb) sum_tu S_tu 2^-7(t+u),
+ *          summed in FP64 (compensated, t then u ascending).
+ *     A row or column holding a non-finite value gives NaN.
  *
  * Built with -O2 -fopenmp -ffp-contract=off and no fast-math, so results are
  * reproducible on any x86-64 host.
@@ -180,6 +197,96 @@ static void acc_add(accum *a, double t, int compensated) {
   }
 }
 
+/* Element offsets of A and B for the label values in idx[]. */
+static void addresses(const problem *p, const int64_t *idx, int64_t *offA, int64_t *offB) {
+  int64_t oa = 0, ob = 0;
+  for (int l = 0; l < p->nlab; ++l) {
+    oa += idx[l] * p->sA[l];
+    ob += idx[l] * p->sB[l];
+  }
+  *offA = oa;
+  *offB = ob;
+}
+
+/* Odometer step over the summed labels, first summed label fastest. */
+static void next_summed(const problem *p, int64_t *idx) {
+  for (int s = 0; s < p->nsum; ++s) {
+    int l = p->sum_lab[s];
+    if (++idx[l] < p->ext[l]) break;
+    idx[l] = 0;
+  }
+}
+
+#define ORACLE_INT8_BASE 16
+#define ORACLE_INT8_MAX_SLICES 12
+
+/* Step 1 of the slicing: the smallest integer e with amax < 2^e (amax >= 0,
+ * finite); 0 when amax == 0. */
+static int scale_exponent(double amax) {
+  if (amax == 0.0) return 0;
+  int e;
+  (void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */
+  return e;
+}
+
+/* Step 2: the s digits of v = x 2^-e (|v| < 1), by exact truncation. */
+static void int8_digits(double x, int e, int s, int *d) {
+  double r = ldexp(x, -e);
+  for (int t = 0; t < s; ++t) {
+    double y = ldexp(r, 7);
+    double q = trunc(y);
+    d[t] = (int)q;
+    r = y - q;
+  }
+}
+
+void oracle_int8_digits(const double *x, int64_t n, int e, int s, int8_t *out) {
+  int d[ORACLE_INT8_MAX_SLICES];
+  for (int64_t i = 0; i < n; ++i) {
+    int8_digits(x[i], e, s, d);
+    for (int t = 0; t < s; ++t) out[i * s + t] = (int8_t)d[t];
+  }
+}
+
+/* Steps 1-4 for one output entry; returns the product term (before alpha)
+ * and fills *abssum with sum |a b|. */
+static double int8_entry(const problem *p, int64_t *idx, const double *a, const double *b, int s,
+                         int64_t terms, double *abssum) {
+  double amax = 0.0, bmax = 0.0, asum = 0.0;
+  int finite = 1;
+  for (int q = 0; q < p->nsum; ++q) idx[p->sum_lab[q]] = 0;
+  for (int64_t t = 0; t < terms; ++t) {
+    int64_t offA, offB;
+    addresses(p, idx, &offA, &offB);
+    double x = a[offA], y = b[offB];
+    if (!isfinite(x) || !isfinite(y)) finite = 0;
+    if (fabs(x) > amax) amax = fabs(x);
+    if (fabs(y) > bmax) bmax = fabs(y);
+    asum += fabs(x * y);
+    next_summed(p, idx);
+  }
+  *abssum = asum;
+  if (!finite) return NAN;
+  const int ea = scale_exponent(amax), eb = scale_exponent(bmax);
+  int64_t S[ORACLE_INT8_MAX_SLICES + 1][ORACLE_INT8_MAX_SLICES + 1];
+  memset(S, 0, sizeof S);
+  int da[ORACLE_INT8_MAX_SLICES], db[ORACLE_INT8_MAX_SLICES];
+  for (int q = 0; q < p->nsum; ++q) idx[p->sum_lab[q]] = 0;
+  for (int64_t t = 0; t < terms; ++t) {
+    int64_t offA, offB;
+    addresses(p, idx, &offA, &offB);
+    int8_digits(a[offA], ea, s, da);
+    int8_digits(b[offB], eb, s, db);
+    for (int i = 1; i <= s; ++i)
+      for (int j = 1; i + j <= s + 1; ++j) S[i][j] += (int64_t)da[i - 1] * (int64_t)db[j - 1];
+    next_summed(p, idx);
+  }
+  accum acc = {0.0, 0.0, 0.0};
+  for (int i = 1; i <= s; ++i)
+    for (int j = 1; i + j <= s + 1; ++j) acc_add(&acc, ldexp((double)S[i][j], -7 * (i + j)), 1);
+  return ldexp(acc.sum + acc.comp, ea + eb);
+}
+
 /* Sum over the summed labels for one output entry whose label values are in
  * idx[] (output slots filled, summed slots overwritten here). */
 static void one_entry(const problem *p, int64_t *idx, const double *a, const double *b,
@@ -187,13 +294,15 @@ static void one_entry(const problem *p, int64_t *idx, const double *a, const dou
   accum acc = {0.0, 0.0, 0.0};
   int64_t terms = 1;
   for (int s = 0; s < p->nsum; ++s) terms *= p->ext[p->sum_lab[s]];
+  if (split > ORACLE_INT8_BASE) {
+    acc.sum = int8_entry(p, idx, a, b, split - ORACLE_INT8_BASE, terms, &acc.abssum);
+    *out = acc;
+    return;
+  }
   for (int s = 0; s < p->nsum; ++s) idx[p->sum_lab[s]] = 0;
   for (int64_t t = 0; t < terms; ++t) {
-    int64_t offA = 0, offB = 0;
-    for (int l = 0; l < p->nlab; ++l) {
-      offA += idx[l] * p->sA[l];
-      offB += idx[l] * p->sB[l];
-    }
+    int64_t offA, offB;
+    addresses(p, idx, &offA, &offB);
     double x = a[offA], y = b[offB];
     acc.abssum += fabs(x * y);
     if (split == 1) {
@@ -218,12 +327,7 @@ static void one_entry(const problem *p, int64_t *idx, const double *a, const dou
     } else {
       acc_add(&acc, x * y, compensated);
     }
-    /* odometer step, first summed label fastest */
-    for (int s = 0; s < p->nsum; ++s) {
-      int l = p->sum_lab[s];
-      if (++idx[l] < p->ext[l]) break;
-      idx[l] = 0;
-    }
+    next_summed(p, idx);
   }
   *out = acc;
 }
@@ -246,6 +350,9 @@ int oracle_contract(double alpha, const oracle_tensor *A, const double *a,
   int rc = analyse(A, B, C, &p);
   if (rc) return rc;
   if (!c || (alpha != 0.0 && (!a || !b))) return ORACLE_ERR_ARG;
+  if (split < 0 || (split > 2 && split <= ORACLE_INT8_BASE) ||
+      split > ORACLE_INT8_BASE + ORACLE_INT8_MAX_SLICES)
+    return ORACLE_ERR_ARG;
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
   for (int64_t e = 0; e < p.nentries; ++e) {
@@ -283,6 +390,9 @@ int oracle_contract_entries(double alpha, const oracle_tensor *A, const double *
   if (n < 0 || (n > 0 && (!cidx || !out))) return ORACLE_ERR_ARG;
   if (beta != 0.0 && n > 0 && !c0) return ORACLE_ERR_ARG;
   if (alpha != 0.0 && (!a || !b)) return ORACLE_ERR_ARG;
+  if (split < 0 || (split > 2 && split <= ORACLE_INT8_BASE) ||
+      split > ORACLE_INT8_BASE + ORACLE_INT8_MAX_SLICES)
+    return ORACLE_ERR_ARG;
   for (int64_t i = 0; i < n; ++i)
     for (int m = 0; m < p.nout; ++m) {
       int64_t v = cidx[i * p.nout + m];

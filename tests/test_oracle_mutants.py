@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from tests import test_oracle as pins
+from tests import test_oracle_int8 as pins8
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -20,7 +21,7 @@ MUTANTS = [
     ("compensation sign", "a->comp += (a->sum - s) + t;", "a->comp += (a->sum - s) - t;"),
     ("compensation dropped at the end", "double ab = compensated ? acc->sum + acc->comp : acc->sum;",
      "double ab = acc->sum;"),
-    ("B addressed with A's strides", "offB += idx[l] * p->sB[l];", "offB += idx[l] * p->sA[l];"),
+    ("B addressed with A's strides", "ob += idx[l] * p->sB[l];", "ob += idx[l] * p->sA[l];"),
     ("odometer stops one short", "if (++idx[l] < p->ext[l]) break;",
      "if (++idx[l] < p->ext[l] - 1) break;"),
     ("diagonal strides overwritten", "p->sA[slot] += A->strides[d];", "p->sA[slot] = A->strides[d];"),
@@ -45,6 +46,19 @@ MUTANTS = [
     ("output digits row-major", "idx[p.out_lab[m]] = rem % ext;\n      rem /= ext;",
      "idx[p.out_lab[m]] = rem % ext;\n      rem /= (m == 0 ? 1 : ext);"),
     ("alpha ignored", "if (alpha != 0.0) r = alpha * ab;", "if (alpha != 0.0) r = ab;"),
+    ("int8 drops the last digit diagonal",
+     "for (int j = 1; i + j <= s + 1; ++j) S[i][j] +=", "for (int j = 1; i + j <= s; ++j) S[i][j] +="),
+    ("int8 digits rounded instead of truncated", "double q = trunc(y);", "double q = nearbyint(y);"),
+    ("int8 scale exponent one too small", "(void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */\n  return e;",
+     "(void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */\n  return e - 1;"),
+    ("int8 digits in base 2^8", "double y = ldexp(r, 7);", "double y = ldexp(r, 8);"),
+    ("int8 B sliced with A's scale", "int8_digits(b[offB], eb, s, db);", "int8_digits(b[offB], ea, s, db);"),
+    ("int8 pair weight off by one digit", "ldexp((double)S[i][j], -7 * (i + j))",
+     "ldexp((double)S[i][j], -7 * (i + j - 1))"),
+    ("int8 row and column scales dropped", "return ldexp(acc.sum + acc.comp, ea + eb);",
+     "return acc.sum + acc.comp;"),
+    ("int8 non-finite rows not flagged", "if (!finite) return NAN;", "if (0) return NAN;"),
+    ("int8 row max over B", "if (fabs(x) > amax) amax = fabs(x);", "if (fabs(y) > amax) amax = fabs(y);"),
 ]
 
 CHECKS = [
@@ -65,6 +79,13 @@ CHECKS = [
     lambda: pins.test_bf16x6_split_matches_library_split(None),
     lambda: pins.test_bf16x6_error_bound(None),
     lambda: pins.test_golden_fixtures(None),
+    lambda: pins8.test_digits_definition(None),
+    lambda: [pins8.test_bruteforce_exact_rational(None, s) for s in range(8)],
+    lambda: [pins8.test_integer_inputs_exact(None, s) for s in range(4)],
+    lambda: pins8.test_kronecker_closed_form(None),
+    lambda: pins8.test_power_of_two_scaling(None),
+    lambda: pins8.test_error_bound_and_convergence(None),
+    lambda: pins8.test_nonfinite_rows_give_nan(None),
 ]
 
 
