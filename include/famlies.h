@@ -254,6 +254,28 @@ famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags)
  * is then unchanged). */
 famlies_status famlies_load_tune_table(famlies_handle h, const char *table_path);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * famlies_plan_contract and famlies_execute in one call that allocates
+ * nothing on the device.  The plan is made on the host and its device data
+ * -- the indexing vectors and any split-K partial sums -- are placed in one
+ * static device array of the library (64 MiB per device, held until the
+ * process ends) instead of plan-owned allocations.  Arguments as for the two
+ * calls it combines (h from famlies_create; A, B, C descriptors; a, b, c
+ * device pointers to the elements with all-zero multi-index).
+ * The call copies the indexing vectors into the array on `stream` and waits
+ * for that stream (so earlier work on it has finished), then launches the
+ * contraction asynchronously; it is not capturable into a graph.  Every call
+ * on a device shares that device's array: calls on one stream are ordered,
+ * calls that overlap in time on one device (other streams, other threads)
+ * race and must not be made.  UNSUPPORTED when the indexing vectors and the
+ * partial sums need more than 64 MiB (the message gives the size); other
+ * errors as for the two calls. */
+famlies_status famlies_contract_noalloc(famlies_handle h, int dtype, int compute, double alpha,
+                                        const famlies_tensor *A, const void *a, const famlies_tensor *B,
+                                        const void *b, double beta, const famlies_tensor *C, void *c,
+                                        void *stream);
+
 const char *famlies_last_error(void);
 const char *famlies_version(void);
 

@@ -80,7 +80,7 @@ EXPORTS = [
     "famlies_version", "famlies_pack_size", "famlies_pack", "famlies_execute_packed",
     "famlies_network_create", "famlies_network_add_tensor", "famlies_network_add_contraction",
     "famlies_network_compile", "famlies_network_bind", "famlies_network_tensor_ptr",
-    "famlies_network_execute", "famlies_network_destroy",
+    "famlies_network_execute", "famlies_network_destroy", "famlies_contract_noalloc",
 ]
 FAMLIES_NET_PACK_A = 1
 FAMLIES_NET_PACK_B = 2
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "famlies_network_tensor_ptr": ([vp, i32, ctypes.POINTER(vp)], i32),
             "famlies_network_execute": ([vp, vp], i32),
             "famlies_network_destroy": ([vp], i32),
+            "famlies_contract_noalloc": ([vp, i32, i32, dbl, T, vp, T, vp, dbl, T, vp, vp], i32),
             "famlies_last_error": ([], ctypes.c_char_p),
             "famlies_version": ([], ctypes.c_char_p),
         }
@@ -195,6 +196,14 @@ def famlies_execute(plan: int, alpha: float, A_ptr: int, B_ptr: int, beta: float
                     stream: int = 0) -> None:
     _check(load_library().famlies_execute(plan, float(alpha), A_ptr, B_ptr, float(beta), C_ptr,
                                           stream), "famlies_execute")
+
+
+def famlies_contract_noalloc(handle: int, dtype: int, compute: int, alpha: float, A: famlies_tensor,
+                             A_ptr: int, B: famlies_tensor, B_ptr: int, beta: float, C: famlies_tensor,
+                             C_ptr: int, stream: int = 0) -> None:
+    _check(load_library().famlies_contract_noalloc(handle, dtype, compute, float(alpha), ctypes.byref(A), A_ptr,
+                                                   ctypes.byref(B), B_ptr, float(beta), ctypes.byref(C), C_ptr,
+                                                   stream), "famlies_contract_noalloc")
 
 
 def famlies_pack_size(plan: int, operand: int) -> int:

@@ -20,7 +20,36 @@
 #include "launch.hpp"
 #include "runtime.hpp"
 
+// Device scratch of famlies_contract_noalloc: the indexing vectors and
+// split-K partial sums of the call in flight, one copy per device, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel or
+// a copy (in host code the name is only a stand-in): the device address is
+// resolved per device with hipGetSymbolAddress and kept (g_scratch_addr).
+static constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace famlies {
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[64] = {};
+
+// The scratch array's address on `device` (resolved once, with that device
+// current).
+static famlies_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= 64) return fail(FAMLIES_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the device");
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(FAMLIES_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_addr[device] = ptr;
+  }
+  *out = g_scratch_addr[device];
+  return FAMLIES_OK;
+}
 
 famlies_status hip_fail(hipError_t e, const char* what) {
   set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -38,7 +67,7 @@ DeviceGuard::~DeviceGuard() {
 }
 
 template <typename OffT>
-static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp) {
+static famlies_status index_image(famlies_plan_s* p, int64_t mp, int64_t np, int64_t kp, std::vector<char>* image) {
   const Analysis& an = p->an;
   std::vector<int64_t> v[9];
   offsets(an.I, 0, an.M, mp, v[0]);
@@ -58,7 +87,8 @@ static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t 
   for (int i = 0; i < 6; ++i) n6 += v[i].size();
   const size_t b6 = (n6 * sizeof(OffT) + 7) & ~(size_t)7;
   const size_t total = b6 + 3 * (size_t)an.L * sizeof(int64_t);
-  std::vector<char> host(total, 0);
+  std::vector<char>& host = *image;
+  host.assign(total, 0);
   OffT* o = reinterpret_cast<OffT*>(host.data());
   size_t pos = 0;
   for (int i = 0; i < 6; ++i) {
@@ -83,10 +113,6 @@ static famlies_status upload(famlies_plan_s* p, int64_t mp, int64_t np, int64_t 
                     !offsets_in_span(v[3], an.N, v[2], an.K, v[7], an.L, y_lo, y_hi))) ||
       !offsets_in_span(v[4], an.M, v[5], an.N, v[8], an.L, an.c_lo, an.c_hi))
     return fail(FAMLIES_ERR_BOUNDS, "planner: an indexing vector addresses outside its tensor's span");
-  hipError_t e = hipMalloc(&p->d_off, total);
-  if (e != hipSuccess) return hip_fail(e, "hipMalloc(indexing vectors)");
-  e = hipMemcpy(p->d_off, host.data(), total, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(indexing vectors)");
   return FAMLIES_OK;
 }
 
@@ -128,12 +154,13 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   return a;
 }
 
-famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int compute,
-                         const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
-                         const TileCfg* force) {
-  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
-  *out = nullptr;
-  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
+// Planning decisions and the host image of the indexing vectors, touching no
+// device memory: p->cfg, the split settlement, the loader flags, the vector
+// positions and p->work_bytes (the split-K workspace the plan needs).
+// *image is left empty when C has no elements.
+static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int dtype, int compute,
+                                   const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                                   const TileCfg* force, std::vector<char>* image) {
   Analysis an;
   std::string err;
   int st = analyze(dtype, compute, A, B, C, &an, &err);
@@ -141,16 +168,6 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   const int64_t lim = kMaxGemmDim;
   if (an.M > lim || an.N > lim || an.K > lim || an.L > lim)
     return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
-  DeviceGuard dg(h->device);
-  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
-  auto* p = new (std::nothrow) famlies_plan_s();
-  if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
-  struct Owner {  // frees the plan if planning throws (host allocation failure)
-    famlies_plan_s** q;
-    ~Owner() {
-      if (*q) delete *q;
-    }
-  } owner{&p};
   p->h = h;
   p->an = an;
   p->cfg = force ? *force : choose_tiles(h, an, &p->table_hit);
@@ -189,29 +206,55 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
   if (an.L > 1) p->cfg.split = 1;  // batch modes already multiply the tile count
   const int64_t ntiles = ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn);
   finalize_split(&p->cfg, an.K, ntiles, &p->kchunk, &p->head);
-  if (ntiles * p->cfg.split * an.L >= ((int64_t)1 << 31)) {
+  if (ntiles * p->cfg.split * an.L >= ((int64_t)1 << 31))
     return fail(FAMLIES_ERR_UNSUPPORTED, "the tile grid exceeds 2^31 workgroups");
+  image->clear();
+  p->work_bytes = 0;
+  if (an.M == 0 || an.N == 0) return FAMLIES_OK;
+  const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
+  const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
+  const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
+  st = p->index_bits == 32 ? index_image<uint32_t>(p, mp, np, kp, image)
+                           : index_image<int64_t>(p, mp, np, kp, image);
+  if (st != FAMLIES_OK) return st;
+  if (p->cfg.split > 1 && an.K > 0) {
+    // plain kernels: one BM x BN block per split tile and K slice; bf16
+    // kernels: one padded M x N plane of FP64 sums per K slice
+    p->work_bytes = ns ? (size_t)p->cfg.split * (size_t)mp * (size_t)np * 8
+                       : (size_t)p->cfg.split * (size_t)(ntiles - p->head) * (size_t)p->cfg.bm *
+                             (size_t)p->cfg.bn * (size_t)an.esize;
   }
-  const bool empty = an.M == 0 || an.N == 0;
-  if (!empty) {
-    const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
-    const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
-    const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
-    st = p->index_bits == 32 ? upload<uint32_t>(p, mp, np, kp) : upload<int64_t>(p, mp, np, kp);
-    if (st != FAMLIES_OK) {
-      return st;
+  return FAMLIES_OK;
+}
+
+famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int compute,
+                         const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                         const TileCfg* force) {
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: null output pointer");
+  *out = nullptr;
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_contract: invalid handle");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
+  auto* p = new (std::nothrow) famlies_plan_s();
+  if (!p) return fail(FAMLIES_ERR_ALLOC, "out of host memory");
+  struct Owner {  // frees the plan on every early return and if planning throws
+    famlies_plan_s** q;
+    ~Owner() {
+      if (*q) delete *q;
     }
-    if (p->cfg.split > 1 && an.K > 0) {
-      // plain kernels: one BM x BN block per split tile and K slice; bf16
-      // kernels: one padded M x N plane of FP64 sums per K slice
-      p->work_bytes = ns ? (size_t)p->cfg.split * (size_t)mp * (size_t)np * 8
-                         : (size_t)p->cfg.split * (size_t)(ntiles - p->head) * (size_t)p->cfg.bm *
-                               (size_t)p->cfg.bn * (size_t)an.esize;
-      hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
-      if (e != hipSuccess) {
-        return hip_fail(e, "hipMalloc(split-K workspace)");
-      }
-    }
+  } owner{&p};
+  std::vector<char> image;
+  famlies_status st = prepare_plan(h, p, dtype, compute, A, B, C, force, &image);
+  if (st != FAMLIES_OK) return st;
+  if (!image.empty()) {
+    hipError_t e = hipMalloc(&p->d_off, image.size());
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(indexing vectors)");
+    e = hipMemcpy(p->d_off, image.data(), image.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(indexing vectors)");
+  }
+  if (p->work_bytes) {
+    hipError_t e = hipMalloc(&p->d_work, p->work_bytes);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(split-K workspace)");
   }
   if (log_enabled()) log_plan(p);
   *out = p;
@@ -232,8 +275,8 @@ void destroy_plan(famlies_plan_s* p) {
 }  // namespace famlies
 
 famlies_plan_s::~famlies_plan_s() {
-  if (d_off) (void)hipFree(d_off);
-  if (d_work) (void)hipFree(d_work);
+  if (owns_device && d_off) (void)hipFree(d_off);
+  if (owns_device && d_work) (void)hipFree(d_work);
   if (batch) famlies::destroy_batch(batch);
 }
 
@@ -260,6 +303,13 @@ famlies_status famlies_create(famlies_handle* out, int device) {
   if (!h) return fail(FAMLIES_ERR_ALLOC, "famlies_create: out of host memory");
   h->device = device;
   h->num_cus = prop.multiProcessorCount;
+  {
+    famlies_status st = scratch_address(device, &h->scratch);
+    if (st != FAMLIES_OK) {
+      delete h;
+      return st;
+    }
+  }
   const char* tt = std::getenv("FAMLIES_TUNE_TABLE");
   if (tt && *tt) {
     std::string err;
@@ -420,6 +470,56 @@ famlies_status famlies_execute_packed(famlies_plan tok, double alpha, const void
                                       void* C, int packed, void* stream) {
   if (packed < 0 || packed > 3) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_execute_packed: packed must be 0..3");
   return execute_impl(plan_of(tok), alpha, A, B, beta, C, packed, stream);
+}
+
+}  // extern "C"
+
+// famlies_plan_contract + famlies_execute in one call whose device data (the
+// indexing vectors and any split-K partial sums) live in the static scratch
+// array instead of plan-owned allocations.
+static famlies_status contract_noalloc_impl(famlies_handle htok, int dtype, int compute, double alpha,
+                                            const famlies_tensor* A, const void* a, const famlies_tensor* B,
+                                            const void* b, double beta, const famlies_tensor* C, void* c,
+                                            void* stream) {
+  famlies_handle_s* h = handle_of(htok);
+  if (!h || !h->scratch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_contract_noalloc: invalid handle");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(FAMLIES_ERR_DEVICE, "cannot select the handle's device");
+  famlies_plan_s p;
+  p.owns_device = false;
+  std::vector<char> image;
+  famlies_status st = prepare_plan(h, &p, dtype, compute, A, B, C, nullptr, &image);
+  if (st != FAMLIES_OK) return st;
+  const size_t off_bytes = (image.size() + 255) & ~(size_t)255;
+  if (off_bytes + p.work_bytes > kNoAllocScratchBytes)
+    return fail(FAMLIES_ERR_UNSUPPORTED,
+                "famlies_contract_noalloc: the call needs " + std::to_string(off_bytes + p.work_bytes) +
+                    " bytes of scratch (indexing vectors and split-K partial sums); the maximum is " +
+                    std::to_string(kNoAllocScratchBytes));
+  p.d_off = h->scratch;
+  p.d_work = p.work_bytes ? static_cast<char*>(h->scratch) + off_bytes : nullptr;
+  if (log_enabled()) log_plan(&p);
+  if (!image.empty()) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // stream-ordered after earlier work on the stream (which may still read
+    // the scratch); the wait lets the host image go when the call returns
+    hipError_t e = hipMemcpyAsync(p.d_off, image.data(), image.size(), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(indexing vectors to scratch)");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
+  return execute_impl(&p, alpha, a, b, beta, c, 0, stream);
+}
+
+extern "C" {
+
+famlies_status famlies_contract_noalloc(famlies_handle h, int dtype, int compute, double alpha,
+                                        const famlies_tensor* A, const void* a, const famlies_tensor* B,
+                                        const void* b, double beta, const famlies_tensor* C, void* c,
+                                        void* stream) {
+  return no_throw("famlies_contract_noalloc", [&] {
+    return contract_noalloc_impl(h, dtype, compute, alpha, A, a, B, b, beta, C, c, stream);
+  });
 }
 
 }  // extern "C"

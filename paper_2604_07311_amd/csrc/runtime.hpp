@@ -44,6 +44,9 @@ struct famlies_handle_s {
   int device = 0;
   int num_cus = 256;
   famlies::TileTable table;
+  // device address of the library's static scratch array on this handle's
+  // device (famlies_contract_noalloc), resolved once when the handle is made
+  void* scratch = nullptr;
 };
 
 struct famlies_plan_s {
@@ -63,6 +66,7 @@ struct famlies_plan_s {
   void* d_work = nullptr;  // split-K partial sums
   size_t work_bytes = 0;
   famlies::BatchPlan* batch = nullptr;  // set for batched plans
+  bool owns_device = true;  // false: d_off / d_work point into the static scratch array
   ~famlies_plan_s();
 };
 
