@@ -30,7 +30,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15}
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "int8": 5.0e15}
 METRIC = "contraction GFLOP/s & % MFMA peak (FP64/FP32/bf16x3) at stated err vs FP64"
 
 
@@ -93,7 +93,7 @@ class Single:
         self.p, self.dtype, self.compute = p, dtype, compute
         self.fm, self.torch = fm, torch
         code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-        comp = {"bf16x3": fm.FAMLIES_BF16X3, "bf16x6": fm.FAMLIES_BF16X6}.get(compute, fm.FAMLIES_NATIVE)
+        comp = fm._compute_code(compute)
         t0 = time.perf_counter()
         self.plan = fm.famlies_plan_contract(fm.handle(0), code, comp,
                                              fm.make_desc(p.a.extents, p.a.strides, p.la),
@@ -383,11 +383,38 @@ def wl_ladder(args):
             out["secondary"][dt]["packed_W"] = rr["packed_W"]
         if "context_torch" in rr:
             out["secondary"][dt]["context_torch"] = rr["context_torch"]
+    if "f64" in probs and not args.no_int8:
+        out.setdefault("secondary", {})["f64_on_int8"] = int8_emulation(args, probs["f64"], r["ms"])
     if not args.no_ring:
         out.setdefault("secondary", {})["ring_o48_v192"] = ring_precisions(args)
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(probs[head])
+    return out
+
+
+def int8_emulation(args, p, native_ms):
+    """The same FP64 ladder with FP64 emulated on INT8 MFMA, six and seven
+    digit slices (21 and 28 INT8 products per FP64 product): FP64-equivalent
+    GFLOP/s (2MNK/t) for the whole call (slicing both operands, then the INT8
+    GEMM), error against the FP64 oracle, speed-up over the native FP64
+    kernel, and a roofline against the INT8 MFMA peak on the INT8 operations
+    issued (products * 2MNK) over the whole call."""
+    out = {}
+    for slices in (6, 7):
+        s = Single(p, "f64", "int8x%d" % slices)
+        check = sample_check(p, s.result_once(), "f64")
+        ms, launch, _ = Timer(s.stream).run(s.step, args.steps, args.warmup)
+        flops = s.info["flops"]
+        prods = slices * (slices + 1) // 2
+        log("ladder f64 on int8x%d: %.3f ms (%.1f GFLOP/s) check %s" % (slices, ms, flops / ms / 1e6, check))
+        s.close()
+        out["int8x%d" % slices] = {
+            "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s (FP64-equivalent, 2MNK/t)",
+            "ms_per_step": round(ms, 4), "slices": slices, "int8_products_per_fp64_product": prods,
+            "speedup_vs_native_fp64": round(native_ms / ms, 3), "error_vs_fp64": check,
+            "pct_fp64_mfma_peak_equivalent": round(100 * flops / (ms * 1e-3) / PEAK["f64"], 2),
+            "roofline": roofline(prods * flops, launch, PEAK["int8"])}
     return out
 
 
@@ -694,6 +721,8 @@ def main():
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-int8", action="store_true",
+                    help="ladder: skip FP64 emulated on INT8 MFMA reported under 'secondary'")
     ap.add_argument("--no-ring", action="store_true",
                     help="ladder: skip the ring in FP32, bf16x3, bf16x6 and FP64 reported under 'secondary'")
     ap.add_argument("--pack", action="store_true",

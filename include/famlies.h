@@ -100,6 +100,26 @@ typedef int32_t famlies_status;
 #define FAMLIES_NATIVE 0
 #define FAMLIES_BF16X3 1
 #define FAMLIES_BF16X6 2
+/* FP64 emulated on INT8 MFMA (FAMLIES_F64 only; new precisions, "Supporting
+ * new and mixed precisions"): every row of the left operand's GEMM view and
+ * every column of the right one is scaled by a power of two 2^-e (e the
+ * smallest integer with max|v| <= (127/128) 2^e), the scaled values are cut
+ * into s signed base-2^7 digits by exact rounding to nearest (|first digit|
+ * <= 127, the others <= 64), the digit products of the pairs (t, u) with
+ * t + u <= s + 1 are summed exactly in int32 on v_mfma_i32_32x32x32_i8
+ * (s(s+1)/2 INT8 products per FP64 product), and the sums are recombined
+ * with alpha, beta and C in FP64 (the error-free splitting of Ozaki, Ogita,
+ * Oishi and Rump in the integer form of Ootomo, Ozaki and Yokota).  Error
+ * against the exact result: at most K (s+4)/4 2^-7s 2^(ex+ey) |alpha| per
+ * entry (ex, ey the scales of its row and column) plus FP64 rounding; a row
+ * or column holding Inf or NaN gives NaN.  FAMLIES_INT8X6: s = 6 (21 INT8
+ * products, about 2^-43 of the row and column scales per product);
+ * FAMLIES_INT8X7: s = 7 (28 products, about 2^-50). */
+#define FAMLIES_INT8X3 19
+#define FAMLIES_INT8X4 20
+#define FAMLIES_INT8X5 21
+#define FAMLIES_INT8X6 22
+#define FAMLIES_INT8X7 23
 
 typedef struct famlies_handle_s *famlies_handle;
 typedef struct famlies_plan_s *famlies_plan;
@@ -127,8 +147,9 @@ typedef struct {
   int32_t tile_m, tile_n, tile_k;
   int32_t split_k;          /* number of K slices (1 = none) */
   int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
-  int32_t kernel;           /* 1 plain, 3 bf16x3, 4 bf16x6 (1 + bf16 parts per operand); +16 / +32 when the kernel reads X / Y
-                               from affine unit-stride K blocks with 16-byte loads (block strides) */
+  int32_t kernel;           /* 1 plain, 3 bf16x3, 4 bf16x6 (1 + bf16 parts per operand), 8 + s FP64 on INT8 with s
+                               slices; +16 / +32 when the kernel reads X / Y from affine unit-stride K blocks with
+                               16-byte loads (block strides) */
   int32_t split_tiles;      /* split_k > 1: how many tiles run as K slices (the last ones in
                                tile order; the others run whole first); 0 without split-K */
   double flops;             /* 2*batch*m*n*k */
@@ -145,8 +166,10 @@ famlies_status famlies_destroy(famlies_handle h);
  * vectors -- the "indexing vectors" of the paper's block-scatter mapping --
  * and upload them; choose tile shape and split-K).  UNSUPPORTED when a GEMM
  * dimension reaches 2^31 - 1024.  dtype is FAMLIES_F64 or
- * FAMLIES_F32; compute is FAMLIES_NATIVE or (F32 only) FAMLIES_BF16X3 or
- * FAMLIES_BF16X6.
+ * FAMLIES_F32; compute is FAMLIES_NATIVE, (F32 only) FAMLIES_BF16X3 or
+ * FAMLIES_BF16X6, or (F64 only) FAMLIES_INT8X3 .. FAMLIES_INT8X7.  An INT8
+ * plan owns a workspace for the digit planes of both operands (s bytes per
+ * element of each GEMM view, padded to its tiles) and their exponents.
  * A label summed inside one input is contracted against a zero stride in
  * the other operand (the product runs over it), so it costs MFMA work. */
 famlies_status famlies_plan_contract(famlies_handle h, famlies_plan *out, int dtype, int compute,

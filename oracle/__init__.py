@@ -198,8 +198,8 @@ def int8_slices(s: int) -> int:
 
 
 def int8_digits(x: np.ndarray, e: int, s: int, lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
-    """The s signed 7-bit digits of each x * 2^-e (|x * 2^-e| < 1), shape
-    x.shape + (s,), int8."""
+    """The s signed digits of each x * 2^-e (|x * 2^-e| <= 127/128), rounded
+    to nearest, shape x.shape + (s,), int8."""
     lib = lib or load()
     src = np.ascontiguousarray(x, dtype=np.float64).ravel()
     out = np.zeros(src.size * int(s), dtype=np.int8)

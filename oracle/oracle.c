@@ -47,11 +47,13 @@
  *     form of Ootomo, Ozaki and Yokota).  For one C entry the "row" of A is
  *     every A element its sum reads, and the "column" of B likewise:
  *       1. each is scaled by a power of two, 2^-ea and 2^-eb, where e is the
- *          smallest integer with max|v| < 2^e (0 for an all-zero row), so
- *          every scaled value lies in (-1, 1);
- *       2. each scaled value v is cut into s signed 7-bit digits, exactly:
- *          r_0 = v, d_t = trunc(2^7 r_{t-1}), r_t = 2^7 r_{t-1} - d_t, so
- *          v = sum_t d_t 2^-7t + 2^-7s r_s with |d_t| <= 127, |r_s| < 1;
+ *          smallest integer with max|v| <= (127/128) 2^e (0 for an all-zero
+ *          row), so every scaled value lies in [-127/128, 127/128];
+ *       2. each scaled value v is cut into s signed digits by exact rounding
+ *          to nearest (ties to even), the extraction of the error-free
+ *          splitting: r_0 = v, d_t = rint(2^7 r_{t-1}), r_t = 2^7 r_{t-1} - d_t,
+ *          so v = sum_t d_t 2^-7t + 2^-7s r_s with |d_1| <= 127,
+ *          |d_t| <= 64 for t >= 2 and |r_s| <= 1/2;
  *       3. for every digit pair (t, u) with t + u <= s + 1 the digit products
  *          are summed over the sum's index space as exact integers S_tu;
  *       4. the entry's product term is 2^(ea+eb) sum_tu S_tu 2^-7(t+u),
@@ -220,21 +222,22 @@ static void next_summed(const problem *p, int64_t *idx) {
 #define ORACLE_INT8_BASE 16
 #define ORACLE_INT8_MAX_SLICES 12
 
-/* Step 1 of the slicing: the smallest integer e with amax < 2^e (amax >= 0,
- * finite); 0 when amax == 0. */
+/* Step 1 of the slicing: the smallest integer e with amax <= (127/128) 2^e
+ * (amax >= 0, finite); 0 when amax == 0. */
 static int scale_exponent(double amax) {
   if (amax == 0.0) return 0;
   int e;
-  (void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */
-  return e;
+  double f = frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */
+  return f <= 127.0 / 128.0 ? e : e + 1;
 }
 
-/* Step 2: the s digits of v = x 2^-e (|v| < 1), by exact truncation. */
+/* Step 2: the s digits of v = x 2^-e (|v| <= 127/128), by exact rounding to
+ * nearest (the default rounding mode: ties to even). */
 static void int8_digits(double x, int e, int s, int *d) {
   double r = ldexp(x, -e);
   for (int t = 0; t < s; ++t) {
     double y = ldexp(r, 7);
-    double q = trunc(y);
+    double q = rint(y);
     d[t] = (int)q;
     r = y - q;
   }

@@ -43,6 +43,11 @@ FAMLIES_F32 = 2
 FAMLIES_NATIVE = 0
 FAMLIES_BF16X3 = 1
 FAMLIES_BF16X6 = 2
+FAMLIES_INT8X3 = 19   # FP64 emulated on INT8 MFMA with 3..7 digit slices (FAMLIES_F64 only)
+FAMLIES_INT8X4 = 20
+FAMLIES_INT8X5 = 21
+FAMLIES_INT8X6 = 22
+FAMLIES_INT8X7 = 23
 
 ERROR_NAMES = {
     FAMLIES_ERR_INVALID_ARG: "INVALID_ARG", FAMLIES_ERR_SHAPE_MISMATCH: "SHAPE_MISMATCH",
@@ -378,7 +383,9 @@ def _compute_code(compute: str) -> int:
         return FAMLIES_BF16X3
     if compute == "bf16x6":
         return FAMLIES_BF16X6
-    raise ValueError("compute must be 'native', 'bf16x3' or 'bf16x6'")
+    if compute in ("int8x3", "int8x4", "int8x5", "int8x6", "int8x7"):
+        return FAMLIES_INT8X3 + int(compute[-1]) - 3
+    raise ValueError("compute must be 'native', 'bf16x3', 'bf16x6' or 'int8x3'..'int8x7'")
 
 
 def _labels(l) -> Tuple[int, ...]:

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libfamlies.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["abi.hip", "planner.cpp", "table.cpp", "plain_kernels.hip", "split_kernels.hip",
-           "batch.hip", "tune.hip", "pack_kernels.hip", "network.cpp", "registry.cpp", "plan_host.cpp"]
+           "batch.hip", "tune.hip", "pack_kernels.hip", "network.cpp", "registry.cpp", "plan_host.cpp", "int8_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CXX = os.environ.get("FAMLIES_CXX", "/opt/rocm/lib/llvm/bin/clang++")

@@ -170,10 +170,14 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
     return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
   p->h = h;
   p->an = an;
-  p->cfg = force ? *force : choose_tiles(h, an, &p->table_hit);
+  const int i8 = int8_slices(compute);
+  p->cfg = i8 ? int8_tile() : force ? *force : choose_tiles(h, an, &p->table_hit);
+  if (i8 && force) p->cfg.index_bits = force->index_bits;
   p->index_bits = p->cfg.index_bits == 64 ? 64 : index_bits_for(an);
   const int ns = split_parts(compute);
-  if (ns) {
+  if (i8) {
+    // fixed tile (int8_tile): no split-K, no tile table
+  } else if (ns) {
     // the bf16 kernels split every tile or none: a tail split becomes none
     if (p->cfg.tail) {
       p->cfg.split = 1;
@@ -217,7 +221,9 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
   st = p->index_bits == 32 ? index_image<uint32_t>(p, mp, np, kp, image)
                            : index_image<int64_t>(p, mp, np, kp, image);
   if (st != FAMLIES_OK) return st;
-  if (p->cfg.split > 1 && an.K > 0) {
+  if (i8 && an.K > 0) {
+    p->work_bytes = int8_work_bytes(i8, an.M, an.N, an.K, an.L);  // digit planes and exponents
+  } else if (p->cfg.split > 1 && an.K > 0) {
     // plain kernels: one BM x BN block per split tile and K slice; bf16
     // kernels: one padded M x N plane of FP64 sums per K slice
     p->work_bytes = ns ? (size_t)p->cfg.split * (size_t)mp * (size_t)np * 8
@@ -362,8 +368,7 @@ famlies_status famlies_plan_destroy(famlies_plan tok) {
 famlies_status famlies_plan_get_info(famlies_plan tok, famlies_plan_info* info) {
   famlies_plan_s* p = plan_of(tok);
   if (!p || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
-  fill_info(p->an, p->cfg, p->index_bits,
-            1 + split_parts(p->an.compute) + (p->x_vec ? 16 : 0) + (p->y_vec ? 32 : 0), info);
+  fill_info(p->an, p->cfg, p->index_bits, kernel_code(p->an, p->x_vec, p->y_vec), info);
   return FAMLIES_OK;
 }
 
@@ -424,7 +429,16 @@ famlies_status execute_impl(famlies_plan_s* p, double alpha, const void* A, cons
   L.kind = (an.K == 0 || alpha == 0.0) ? PlainLaunch::kScale : PlainLaunch::kMain;
   hipError_t e;
   const int ns = split_parts(an.compute);
-  if (ns && L.kind == PlainLaunch::kMain) {
+  const int i8 = int8_slices(an.compute);
+  if (i8 && (pa || pb)) return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_execute_packed: no packed operands for INT8 plans");
+  if (i8 && L.kind == PlainLaunch::kMain) {
+    // slicer read modes: affine K blocks (the plan's block-stride flags, for
+    // slices of 64 and a 16-byte aligned base) with 16-byte loads
+    const int xmode = an.x_kfast ? (p->x_vec && !((uintptr_t)x & 15) ? 2 : 1) : 0;
+    const int ymode = an.y_kfast ? (p->y_vec && !((uintptr_t)y & 15) ? 2 : 1) : 0;
+    e = p->index_bits == 32 ? launch_int8(make_args<uint32_t>(p, x, y, C, alpha, beta), i8, xmode, ymode, s)
+                            : launch_int8(make_args<int64_t>(p, x, y, C, alpha, beta), i8, xmode, ymode, s);
+  } else if (ns && L.kind == PlainLaunch::kMain) {
     if (p->index_bits == 32) {
       PlainArgs<uint32_t> a = make_args<uint32_t>(p, x, y, C, alpha, beta);
       if (xp) {  // the packed buffer is addressed from its start, not through offsets

@@ -125,6 +125,7 @@ famlies_status pack_geom(famlies_plan_s* p, int operand, PackGeom* g) {
   if (operand != 0 && operand != 1) return fail(FAMLIES_ERR_INVALID_ARG, "pack: operand must be 0 (A) or 1 (B)");
   const Analysis& an = p->an;
   const int ns = split_parts(an.compute);
+  if (int8_slices(an.compute)) return fail(FAMLIES_ERR_UNSUPPORTED, "pack: INT8 plans slice their operands themselves");
   g->x = (operand == 0) != an.swapped;
   g->br = g->x ? p->cfg.bm : p->cfg.bn;
   g->bk = p->cfg.bk;

@@ -199,6 +199,21 @@ void all_offsets(const Analysis& an, std::vector<int64_t>* v) {
   for (int i = 0; i < 9; ++i) offsets(*groups[i], which[i], len[i], len[i], v[i]);
 }
 
+int kernel_code(const Analysis& an, bool xv, bool yv) {
+  if (int8_slices(an.compute)) return 8 + int8_slices(an.compute);
+  return 1 + split_parts(an.compute) + (xv ? 16 : 0) + (yv ? 32 : 0);
+}
+
+TileCfg int8_tile() {
+  TileCfg t;
+  t.bm = 128;
+  t.bn = 64;
+  t.bk = 64;
+  t.split = 1;
+  t.tail = 0;
+  return t;
+}
+
 bool log_enabled() {
   static const bool on = [] {
     const char* v = std::getenv("FAMLIES_LOG");
@@ -213,7 +228,11 @@ void log_decision(const char* what, const Analysis& an, const TileCfg& cfg, int 
                   bool y_vec, size_t work_bytes, bool table_hit) {
   static const char* loader[4] = {"rows", "k-gather", "packed", "k-affine"};
   const int xm = an.x_kfast ? (x_vec ? 3 : 1) : 0, ym = an.y_kfast ? (y_vec ? 3 : 1) : 0;
-  const char* comp = an.compute == FAMLIES_BF16X3 ? "bf16x3" : an.compute == FAMLIES_BF16X6 ? "bf16x6" : "native";
+  static const char* int8_names[8] = {"", "", "", "int8x3", "int8x4", "int8x5", "int8x6", "int8x7"};
+  const char* comp = an.compute == FAMLIES_BF16X3   ? "bf16x3"
+                     : an.compute == FAMLIES_BF16X6 ? "bf16x6"
+                     : int8_slices(an.compute)      ? int8_names[int8_slices(an.compute)]
+                                                    : "native";
   std::fprintf(stderr,
                "[famlies] %s %s/%s M=%lld N=%lld K=%lld L=%lld swapped=%d groups=%zu/%zu/%zu/%zu "
                "trace=%d diag=%d X=%s Y=%s tile=%dx%dx%d split=%d split_tiles=%d index_bits=%d "
@@ -243,7 +262,7 @@ static famlies_status analyze_impl(int dtype, int compute, const famlies_tensor*
   if (st != FAMLIES_OK) return fail(st, err);
   if (an.M > kMaxGemmDim || an.N > kMaxGemmDim || an.K > kMaxGemmDim || an.L > kMaxGemmDim)
     return fail(FAMLIES_ERR_UNSUPPORTED, "a GEMM dimension exceeds 2^31 - 1024");
-  TileCfg t = choose_tiles(nullptr, an);
+  TileCfg t = int8_slices(an.compute) ? int8_tile() : choose_tiles(nullptr, an);
   if (split_parts(an.compute) && t.tail) {  // as in make_plan: no split for the bf16 kernels
     t.split = 1;
     t.tail = 0;
@@ -257,7 +276,7 @@ static famlies_status analyze_impl(int dtype, int compute, const famlies_tensor*
     all_offsets(an, v);
     vec_flags(an, t.bk, ib, v, &xv, &yv);
   }
-  fill_info(an, t, ib, 1 + split_parts(an.compute) + (xv ? 16 : 0) + (yv ? 32 : 0), info);
+  fill_info(an, t, ib, kernel_code(an, xv, yv), info);
   if (log_enabled()) log_decision("analyze", an, t, ib, xv, yv, 0, false);
   if (offs) {
     const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N + 3 * an.L;

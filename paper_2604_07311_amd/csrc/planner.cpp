@@ -133,12 +133,17 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
     *err = "dtype must be FAMLIES_F64 or FAMLIES_F32";
     return FAMLIES_ERR_INVALID_ARG;
   }
-  if (compute != FAMLIES_NATIVE && compute != FAMLIES_BF16X3 && compute != FAMLIES_BF16X6) {
-    *err = "compute must be FAMLIES_NATIVE, FAMLIES_BF16X3 or FAMLIES_BF16X6";
+  const bool int8 = compute >= FAMLIES_INT8X3 && compute <= FAMLIES_INT8X7;
+  if (compute != FAMLIES_NATIVE && compute != FAMLIES_BF16X3 && compute != FAMLIES_BF16X6 && !int8) {
+    *err = "compute must be FAMLIES_NATIVE, FAMLIES_BF16X3, FAMLIES_BF16X6 or FAMLIES_INT8X3..FAMLIES_INT8X7";
     return FAMLIES_ERR_INVALID_ARG;
   }
-  if (compute != FAMLIES_NATIVE && dtype != FAMLIES_F32) {
+  if ((compute == FAMLIES_BF16X3 || compute == FAMLIES_BF16X6) && dtype != FAMLIES_F32) {
     *err = "split-bf16 compute needs FAMLIES_F32 data";
+    return FAMLIES_ERR_UNSUPPORTED;
+  }
+  if (int8 && dtype != FAMLIES_F64) {
+    *err = "FP64 emulation on INT8 needs FAMLIES_F64 data";
     return FAMLIES_ERR_UNSUPPORTED;
   }
   if (!check_tensor(A, "A", err) || !check_tensor(B, "B", err) || !check_tensor(C, "C", err))

@@ -137,6 +137,10 @@ int64_t ceil_div(int64_t a, int64_t b);
 // computed whole first (*head; every tile when there is no split).
 void finalize_split(TileCfg* t, int64_t K, int64_t ntiles, int* kchunk, int* head);
 void fill_info(const Analysis& an, const TileCfg& t, int index_bits, int kernel, famlies_plan_info* info);
+// famlies_plan_info.kernel of a plan (xv, yv: affine-block loaders of X, Y).
+int kernel_code(const Analysis& an, bool xv, bool yv);
+// The fixed tile of the INT8 kernels: 128 x 64 outputs, K slices of 64.
+TileCfg int8_tile();
 // 32: uint32 byte offsets from each operand's lowest element (every operand
 // spans less than 4 GiB over its non-batch modes); 64: int64 element offsets.
 int index_bits_for(const Analysis& an);
@@ -156,5 +160,15 @@ hipError_t launch_split(const PlainArgs<uint32_t>& a, const PlainLaunch& L, int 
 hipError_t launch_split(const PlainArgs<int64_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
 bool split_tile_supported(int ns, int bm, int bn);
 inline int split_parts(int compute) { return compute == FAMLIES_BF16X6 ? 3 : compute == FAMLIES_BF16X3 ? 2 : 0; }
+// FP64 on INT8 MFMA: the number of digit slices, 0 for other compute modes.
+inline int int8_slices(int compute) {
+  return compute >= FAMLIES_INT8X3 && compute <= FAMLIES_INT8X7 ? compute - FAMLIES_INT8X3 + 3 : 0;
+}
+// xmode / ymode: 0 row-gathered, 1 K-gathered, 2 K-gathered in affine blocks
+hipError_t launch_int8(const PlainArgs<uint32_t>& a, int slices, int xmode, int ymode, hipStream_t s);
+hipError_t launch_int8(const PlainArgs<int64_t>& a, int slices, int xmode, int ymode, hipStream_t s);
+// Workspace of an INT8 plan: the digit planes of X and Y and their row /
+// column exponents.
+size_t int8_work_bytes(int slices, int64_t M, int64_t N, int64_t K, int64_t L);
 
 }  // namespace famlies

@@ -63,7 +63,7 @@ class GpuRunner:
     def plan(self, p: synth.Problem, dtype: str, compute: str = "native"):
         fm = self.fm
         code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-        comp = {"bf16x3": fm.FAMLIES_BF16X3, "bf16x6": fm.FAMLIES_BF16X6}.get(compute, fm.FAMLIES_NATIVE)
+        comp = fm._compute_code(compute)
         return fm.famlies_plan_contract(self.h, code, comp,
                                         fm.make_desc(p.a.extents, p.a.strides, p.la),
                                         fm.make_desc(p.b.extents, p.b.strides, p.lb),

@@ -1,15 +1,15 @@
 """Pins for the oracle's FP64 emulation on 8-bit integer products (CPU only).
 
 The oracle (``split = oracle.int8_slices(s)``) scales each row of A's and
-each column of B's GEMM view by a power of two into (-1, 1), cuts the scaled
-values into s signed 7-bit digits by exact truncation, sums the digit
-products of the pairs (t, u) with t + u <= s + 1 as exact integers and
-recombines them in FP64.  Each check ties it to something other than itself:
-an exact-rational re-implementation of those steps written here with
-``fractions``, integer inputs (where one digit is exact and the emulation
-must equal the plain contraction bit for bit), a closed form with a
-Kronecker-delta operand (the emulation then returns A truncated toward zero
-to 7s bits below its row scale), power-of-two scaling, and the truncation
+each column of B's GEMM view by a power of two into [-127/128, 127/128],
+cuts the scaled values into s signed digits by exact rounding to nearest in
+base 2^7, sums the digit products of the pairs (t, u) with t + u <= s + 1 as
+exact integers and recombines them in FP64.  Each check ties it to something
+other than itself: an exact-rational re-implementation of those steps
+written here with ``fractions``, integer inputs (where one digit is exact and
+the emulation must equal the plain contraction bit for bit), a closed form
+with a Kronecker-delta operand (the emulation then returns A rounded to the
+nearest multiple of 2^-7s of its row scale), power-of-two scaling, and the
 error bound against the exact FP64 contraction."""
 import itertools
 import math
@@ -25,30 +25,38 @@ from tests.test_oracle import _random_roles_problem
 
 
 def _exp(vmax):
-    """Smallest integer e with vmax < 2^e (0 for 0), from the definition."""
+    """Smallest integer e with vmax <= (127/128) 2^e (0 for 0), from the
+    definition."""
     if vmax == 0:
         return 0
+    lim = Fraction(127, 128)
     e = 0
-    while Fraction(vmax) >= Fraction(2) ** e:
+    while Fraction(vmax) > lim * Fraction(2) ** e:
         e += 1
-    while Fraction(vmax) < Fraction(2) ** (e - 1):
+    while Fraction(vmax) <= lim * Fraction(2) ** (e - 1):
         e -= 1
     return e
 
 
+def _rne(w):
+    """Nearest integer to the rational w, ties to the even one."""
+    q = math.floor(w + Fraction(1, 2))
+    if w + Fraction(1, 2) == q and q % 2:
+        q -= 1
+    return q
+
+
 def _digits(x, e, s):
-    """Digits of x 2^-e by the textbook rule on exact rationals: the first
-    7s fractional bits of |v| in base 128, with v's sign."""
+    """Digits of v = x 2^-e on exact rationals: repeatedly the nearest
+    integer to 128 times the remainder."""
     v = Fraction(x) / Fraction(2) ** e
-    assert abs(v) < 1
-    sign = -1 if v < 0 else 1
-    w = abs(v)
+    assert abs(v) <= Fraction(127, 128)
     out = []
     for _ in range(s):
-        w *= 128
-        q = math.floor(w)
-        out.append(sign * q)
-        w -= q
+        v *= 128
+        q = _rne(v)
+        out.append(q)
+        v -= q
     return out
 
 
@@ -92,16 +100,17 @@ def _brute_int8(alpha, a, la, b, lb, beta, c, lc, s):
 
 def test_digits_definition(oracle_lib):
     rng = np.random.default_rng(11)
-    x = np.concatenate([rng.uniform(-1, 1, 300) * 0.999, [0.0, -0.0, 0.5, -0.5, 2.0 ** -30, 127 / 128]])
+    ties = [(2 * k + 1) * 2.0 ** -8 for k in range(-63, 63)]   # v 2^7 = half-integers
+    x = np.concatenate([rng.uniform(-1, 1, 300) * (127 / 128), ties,
+                        [0.0, -0.0, 0.5, -0.5, 2.0 ** -30, 127 / 128, -127 / 128, 3 * 2.0 ** -15]])
     for s in (1, 3, 7, 9):
         d = oracle.int8_digits(x, 0, s)
         for i, xi in enumerate(x):
             assert list(d[i]) == _digits(xi, 0, s)
-        assert np.all(np.abs(d) <= 127)
-        # v = sum d_t 2^-7t + remainder, |remainder| < 2^-7s, same sign as v
+        assert np.all(np.abs(d[:, 0]) <= 127) and np.all(np.abs(d[:, 1:]) <= 64)
+        # v = sum d_t 2^-7t + remainder, |remainder| <= 2^-7s / 2
         rec = (d.astype(np.float64) * 2.0 ** (-7 * np.arange(1, s + 1))).sum(axis=1)
-        assert np.all(np.abs(x - rec) < 2.0 ** (-7 * s))
-        assert np.all((x - rec) * x >= 0)
+        assert np.all(np.abs(x - rec) <= 2.0 ** (-7 * s - 1))
     # scaled rows: x 2^-e
     y = rng.uniform(-6, 6, 50)
     d = oracle.int8_digits(y, 3, 4)
@@ -158,13 +167,17 @@ def test_integer_inputs_exact(oracle_lib, seed):
 
 def test_kronecker_closed_form(oracle_lib):
     """B[e,b,f,j] = delta(e,b) delta(f,j): every column of B's view holds one
-    1 (scale 2^1, digit 64), so the emulation returns each A entry truncated
-    toward zero to 7s bits below its row's scale 2^ea:
-    C[a,b,i,j] = alpha 2^(ea-7s) trunc(A[a,b,i,j] 2^(7s-ea)) + beta C0."""
+    1 (scale 2^1, digit 64), so the emulation returns each A entry rounded to
+    the nearest multiple of 2^-7s of its row's scale 2^ea (ties to even):
+    C[a,b,i,j] = alpha 2^(ea-7s) rint(A[a,b,i,j] 2^(7s-ea)) + beta C0, with
+    ea the smallest e such that the row's max|A| <= (127/128) 2^e."""
     n = 4
     rng = np.random.default_rng(17)
     p = synth.plain16(seed=17, n=n)
     abuf = synth.values(rng, p.a.size, "outliers")
+    A4w = abuf.reshape((n,) * 4, order="F")              # a view: writes go to abuf
+    A4w[1, 2, 0, 3] = 0.999 * 8 * np.sign(A4w[1, 2, 0, 3]) * max(1.0, np.abs(A4w[1, :, 0, :]).max() / 8)
+    A4w[3, :, 2, :] = A4w[3, :, 2, :] / np.abs(A4w[3, :, 2, :]).max() * (255 / 256)   # row max in (127/128, 1)
     bbuf = np.zeros(p.b.size)
     for e in range(n):
         for f in range(n):
@@ -181,10 +194,11 @@ def test_kronecker_closed_form(oracle_lib):
         for a_ in range(n):
             for i in range(n):
                 row = A4[a_, :, i, :]
-                ea = math.frexp(float(np.abs(row).max()))[1]
+                ea = _exp(float(np.abs(row).max()))
                 for b_ in range(n):
                     for j in range(n):
-                        t = math.ldexp(math.trunc(math.ldexp(float(A4[a_, b_, i, j]), 7 * s - ea)), ea - 7 * s)
+                        t = math.ldexp(float(np.rint(math.ldexp(float(A4[a_, b_, i, j]), 7 * s - ea))),
+                                       ea - 7 * s)
                         want[a_, b_, i, j] = t + 0.5 * C0[a_, b_, i, j]
         np.testing.assert_array_equal(out.reshape((n,) * 4, order="F"), want)
 
@@ -206,8 +220,9 @@ def test_power_of_two_scaling(oracle_lib):
 
 
 def test_error_bound_and_convergence(oracle_lib):
-    """Against the exact FP64 contraction: each product is off by less than
-    (s+2) 2^-7s 2^(ea+eb) (truncated digits and dropped pairs), plus FP64
+    """Against the exact FP64 contraction: each product is off by at most
+    (s+4)/4 2^-7s 2^(ea+eb) (rounded digits: 2^-7s-1 per operand; dropped
+    pairs: s-1 products of two digits <= 64 at weight 2^-7(s+2)), plus FP64
     rounding; and each extra slice shrinks the error by about 2^7."""
     p = synth.plain16(seed=23, n=8)
     rng = np.random.default_rng(23)
@@ -221,15 +236,15 @@ def test_error_bound_and_convergence(oracle_lib):
     n = 8
     A4 = abuf.reshape((n,) * 4, order="F")
     B4 = bbuf.reshape((n,) * 4, order="F")
-    ea = np.array([[math.frexp(float(np.abs(A4[a_, :, i, :]).max()))[1] for i in range(n)] for a_ in range(n)])
-    eb = np.array([[math.frexp(float(np.abs(B4[:, b_, :, j]).max()))[1] for j in range(n)] for b_ in range(n)])
+    ea = np.array([[_exp(float(np.abs(A4[a_, :, i, :]).max())) for i in range(n)] for a_ in range(n)])
+    eb = np.array([[_exp(float(np.abs(B4[:, b_, :, j]).max())) for j in range(n)] for b_ in range(n)])
     scale = np.exp2(ea[:, None, :, None] + eb[None, :, None, :]).reshape(-1, order="F")   # C[a,b,i,j]
     K = n * n
     errs = []
     for s in (2, 3, 4, 5, 6, 7):
         got = oracle.contract(1.0, A, p.la, B, p.lb, 0.0, C, p.lc, split=oracle.int8_slices(s))
         err = np.abs(got - exact)
-        bound = K * (s + 2) * 2.0 ** (-7 * s) * scale + 8 * 2.0 ** -53 * (d + np.abs(exact))
+        bound = K * (s + 4) / 4 * 2.0 ** (-7 * s) * scale + 8 * 2.0 ** -53 * (d + np.abs(exact))
         assert np.all(err <= bound), s
         errs.append(np.linalg.norm(got - exact))
     for e0, e1 in zip(errs[:-2], errs[1:-1]):

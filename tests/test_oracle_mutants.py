@@ -48,9 +48,10 @@ MUTANTS = [
     ("alpha ignored", "if (alpha != 0.0) r = alpha * ab;", "if (alpha != 0.0) r = ab;"),
     ("int8 drops the last digit diagonal",
      "for (int j = 1; i + j <= s + 1; ++j) S[i][j] +=", "for (int j = 1; i + j <= s; ++j) S[i][j] +="),
-    ("int8 digits rounded instead of truncated", "double q = trunc(y);", "double q = nearbyint(y);"),
-    ("int8 scale exponent one too small", "(void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */\n  return e;",
-     "(void)frexp(amax, &e); /* amax = f 2^e, 0.5 <= f < 1 */\n  return e - 1;"),
+    ("int8 digits truncated instead of rounded", "double q = rint(y);", "double q = trunc(y);"),
+    ("int8 scale exponent ignores the 127/128 limit", "return f <= 127.0 / 128.0 ? e : e + 1;", "return e;"),
+    ("int8 scale exponent one too large", "return f <= 127.0 / 128.0 ? e : e + 1;",
+     "return f <= 127.0 / 128.0 ? e + 1 : e + 2;"),
     ("int8 digits in base 2^8", "double y = ldexp(r, 7);", "double y = ldexp(r, 8);"),
     ("int8 B sliced with A's scale", "int8_digits(b[offB], eb, s, db);", "int8_digits(b[offB], ea, s, db);"),
     ("int8 pair weight off by one digit", "ldexp((double)S[i][j], -7 * (i + j))",
