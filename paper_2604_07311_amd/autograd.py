@@ -27,6 +27,12 @@ way back:
 The Function is functional: it never writes into C0.  Gradients take their
 input's strides when that input is dense (torch's preserve_format), so the
 engine accumulates them without a layout copy.
+
+dA and dB do not depend on each other, so when both are needed dB runs on a
+second stream of the same device beside dA (each contraction's last round
+of tiles then overlaps the other's): every tensor is allocated on the
+caller's stream, the second stream waits for the caller's work before it
+starts and the caller's stream waits for it before the gradients are used.
 """
 from __future__ import annotations
 
@@ -36,7 +42,19 @@ from . import _labels
 from . import contract as _contract
 
 
-def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first):
+_side_streams = {}
+
+
+def _side_stream(device):
+    """One extra stream per device (default priority) for dB."""
+    s = _side_streams.get(device)
+    if s is None:
+        s = torch.cuda.Stream(device=device)
+        _side_streams[device] = s
+    return s
+
+
+def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first, stream=None):
     """Gradient with respect to `target` (labels lt): alpha times the
     contraction of G (labels lc) with the other operand (labels lo) onto
     target's labels, in a tensor laid out like target.  Labels are taken as
@@ -50,14 +68,19 @@ def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first):
 
     def run(out, labels):
         if g_first:
-            return _contract(alpha, G, lc, other, lo, 0.0, out, labels, compute=compute)
-        return _contract(alpha, other, lo, G, lc, 0.0, out, labels, compute=compute)
+            return _contract(alpha, G, lc, other, lo, 0.0, out, labels, compute=compute, stream=stream)
+        return _contract(alpha, other, lo, G, lc, 0.0, out, labels, compute=compute, stream=stream)
 
     if len(uniq) == len(lt) and len(kept) == len(uniq):
         grad = torch.empty_like(target, memory_format=torch.preserve_format)
         run(grad, lt)
         return grad
-    grad = torch.zeros_like(target, memory_format=torch.preserve_format)
+    grad = torch.empty_like(target, memory_format=torch.preserve_format)
+    if stream is not None:  # the fill belongs to the stream that writes the gradient
+        with torch.cuda.stream(stream):
+            grad.zero_()
+    else:
+        grad.zero_()
     ext = {ch: target.shape[i] for i, ch in enumerate(lt)}
     stride = {ch: 0 for ch in uniq}
     for i, ch in enumerate(lt):
@@ -66,9 +89,14 @@ def _operand_grad(alpha, G, lc, other, lo, target, lt, compute, g_first):
     if len(kept) == len(uniq):
         run(view, uniq)
     else:
-        red = run(None, kept)  # dense, modes in `kept` order (a subsequence of `uniq`)
+        red = torch.empty([ext[ch] for ch in kept], dtype=target.dtype, device=target.device)
+        run(red, kept)  # modes in `kept` order (a subsequence of `uniq`)
         shape = [ext[ch] if ch in kept else 1 for ch in uniq]
-        view.copy_(red.reshape(shape).expand(view.shape))
+        if stream is not None:
+            with torch.cuda.stream(stream):
+                view.copy_(red.reshape(shape).expand(view.shape))
+        else:
+            view.copy_(red.reshape(shape).expand(view.shape))
     return grad
 
 
@@ -89,10 +117,19 @@ class ContractFn(torch.autograd.Function):
         A, B, C0 = ctx.saved_tensors
         alpha, la, lb, beta, lc, compute, has_c0 = ctx.cfg
         dA = dB = dC0 = None
-        if ctx.needs_input_grad[1]:
+        both = ctx.needs_input_grad[1] and ctx.needs_input_grad[3] and G.is_cuda
+        if both:
+            cur = torch.cuda.current_stream(G.device)
+            side = _side_stream(G.device)
+            side.wait_stream(cur)  # G, A, B and the new gradients' memory are ready
+            dB = _operand_grad(alpha, G, lc, A.detach(), la, B, lb, compute, False, stream=side)
             dA = _operand_grad(alpha, G, lc, B.detach(), lb, A, la, compute, True)
-        if ctx.needs_input_grad[3]:
-            dB = _operand_grad(alpha, G, lc, A.detach(), la, B, lb, compute, False)
+            cur.wait_stream(side)
+        else:
+            if ctx.needs_input_grad[1]:
+                dA = _operand_grad(alpha, G, lc, B.detach(), lb, A, la, compute, True)
+            if ctx.needs_input_grad[3]:
+                dB = _operand_grad(alpha, G, lc, A.detach(), la, B, lb, compute, False)
         if has_c0 and ctx.needs_input_grad[6]:
             dC0 = torch.empty_like(C0, memory_format=torch.preserve_format)
             if beta != 0.0:
