@@ -200,14 +200,25 @@ famlies_status famlies_analyze(int dtype, int compute, const famlies_tensor *A,
 /* Batched: n independent contractions (descriptor arrays of length n) of one
  * dtype, run by one persistent kernel over device work queues of
  * (problem, tile) items (one queue per XCD, drawn with an atomic counter
- * that the kernel clears again before it ends), tile shapes per size class
- * from the handle's tile table (tiles and orientation as in
- * famlies_plan_contract; each descriptor obeys the same rules).  Tensors of different problems may share memory
- * for A and B; C outputs must be disjoint (not checked).  Batch modes are
- * UNSUPPORTED in batched plans. */
+ * that the kernel clears again before it ends).  Each problem's tile is
+ * BM x BN with BM, BN in {64, 128}: the batch entry of the handle's tile
+ * table for its size class (written by famlies_tune from timed batched
+ * launches), else 128 along each of M and N that fills it and 64 otherwise.
+ * Orientation as in famlies_plan_contract; each descriptor obeys the same
+ * rules.  Tensors of different problems may share memory for A and B; C
+ * outputs must be disjoint (not checked).  Batch modes are UNSUPPORTED in
+ * batched plans.  famlies_plan_get_info on a batched plan gives batch = n,
+ * flops = the total, everything else zero. */
 famlies_status famlies_batch_plan(famlies_handle h, famlies_plan *out, int dtype, int64_t n,
                                   const famlies_tensor *A, const famlies_tensor *B,
                                   const famlies_tensor *C);
+
+/* The tile chosen for each problem of a batched plan: tile_m[i] x tile_n[i]
+ * of the kernel view of problem i (after any operand exchange), 0 x 0 for a
+ * problem with nothing to multiply (M, N or K zero).  Both arrays are host
+ * memory of n entries, n equal to the plan's problem count (else
+ * INVALID_ARG). */
+famlies_status famlies_batch_plan_tiles(famlies_plan p, int32_t *tile_m, int32_t *tile_n, int64_t n);
 
 /* A_dev, B_dev, C_dev: device arrays of n device pointers each.  One kernel
  * launch; graph-capturable. */
@@ -260,10 +271,25 @@ famlies_status famlies_network_tensor_ptr(famlies_network n, int32_t id, void **
 famlies_status famlies_network_execute(famlies_network n, void *stream);
 famlies_status famlies_network_destroy(famlies_network n);
 
-/* Autotune: time the candidate tile shapes on synthetic problems of each
- * size class on the handle's device and write the table to table_path
- * (text, one line per class); the handle then uses it.  flags: bit 0 = quick
- * (fewer repetitions). */
+/* Autotune (the measured counterpart of the block-size choices that the
+ * paper's control tree encodes per level, Section "Building on important
+ * advances", "Nesting of algorithms and blockings"): time the candidates on
+ * the handle's device for each size class (ceil(log2) of M, N, K) and write
+ * the winners to table_path (text, one line per class, as read by
+ * famlies_load_tune_table); the handle then uses them.
+ *   plain entries: tile shape and split-K of the single-contraction kernels
+ *     (FP64, FP32 and bf16x3), timed on one GEMM-shaped contraction;
+ *   batch entries: tile class (BM, BN in {64, 128}) of the persistent
+ *     batched kernel (FP64 and FP32), timed on batched launches of that
+ *     kernel with enough identical problems to fill the device.
+ * flags: FAMLIES_TUNE_QUICK (a coarse grid, fewer repetitions),
+ * FAMLIES_TUNE_BATCH_ONLY or FAMLIES_TUNE_PLAIN_ONLY (one kind of entry;
+ * both: INVALID_ARG).  Allocates about 1.6 GB of scratch device memory for
+ * the call.  Errors: INVALID_ARG, ALLOC, DEVICE; on error nothing is
+ * written and the handle's table is unchanged. */
+#define FAMLIES_TUNE_QUICK 1
+#define FAMLIES_TUNE_BATCH_ONLY 2
+#define FAMLIES_TUNE_PLAIN_ONLY 4
 famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags);
 /* Load a table written by famlies_tune (or by hand).  Text, '#' comments,
  * one entry per line:

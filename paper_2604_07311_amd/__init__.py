@@ -48,6 +48,9 @@ FAMLIES_INT8X4 = 20
 FAMLIES_INT8X5 = 21
 FAMLIES_INT8X6 = 22
 FAMLIES_INT8X7 = 23
+FAMLIES_TUNE_QUICK = 1
+FAMLIES_TUNE_BATCH_ONLY = 2
+FAMLIES_TUNE_PLAIN_ONLY = 4
 
 ERROR_NAMES = {
     FAMLIES_ERR_INVALID_ARG: "INVALID_ARG", FAMLIES_ERR_SHAPE_MISMATCH: "SHAPE_MISMATCH",
@@ -86,6 +89,7 @@ EXPORTS = [
     "famlies_network_create", "famlies_network_add_tensor", "famlies_network_add_contraction",
     "famlies_network_compile", "famlies_network_bind", "famlies_network_tensor_ptr",
     "famlies_network_execute", "famlies_network_destroy", "famlies_contract_noalloc",
+    "famlies_batch_plan_tiles",
 ]
 FAMLIES_NET_PACK_A = 1
 FAMLIES_NET_PACK_B = 2
@@ -124,6 +128,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int64), i64], i32),
             "famlies_batch_plan": ([vp, ctypes.POINTER(vp), i32, i64, T, T, T], i32),
             "famlies_batch_execute": ([vp, dbl, dbl, vp, vp, vp, vp], i32),
+            "famlies_batch_plan_tiles": ([vp, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32), i64], i32),
             "famlies_tune": ([vp, ctypes.c_char_p, i32], i32),
             "famlies_load_tune_table": ([vp, ctypes.c_char_p], i32),
             "famlies_pack_size": ([vp, i32, ctypes.POINTER(ctypes.c_size_t)], i32),
@@ -324,6 +330,14 @@ def famlies_batch_plan(handle: int, dtype: int, descs_a, descs_b, descs_c) -> in
     _check(load_library().famlies_batch_plan(handle, ctypes.byref(p), dtype, n, arr[0], arr[1],
                                              arr[2]), "famlies_batch_plan")
     return p.value
+
+
+def famlies_batch_plan_tiles(plan: int, n: int):
+    """Per-problem tile (tile_m, tile_n) of a batched plan of n problems."""
+    tm = (ctypes.c_int32 * max(n, 1))()
+    tn = (ctypes.c_int32 * max(n, 1))()
+    _check(load_library().famlies_batch_plan_tiles(plan, tm, tn, n), "famlies_batch_plan_tiles")
+    return [(tm[i], tn[i]) for i in range(n)]
 
 
 def famlies_batch_execute(plan: int, alpha: float, beta: float, A_ptrs_dev: int, B_ptrs_dev: int,

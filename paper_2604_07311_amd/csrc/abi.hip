@@ -368,6 +368,10 @@ famlies_status famlies_plan_destroy(famlies_plan tok) {
 famlies_status famlies_plan_get_info(famlies_plan tok, famlies_plan_info* info) {
   famlies_plan_s* p = plan_of(tok);
   if (!p || !info) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_plan_get_info: invalid argument");
+  if (p->batch) {
+    batch_info(p->batch, info);
+    return FAMLIES_OK;
+  }
   fill_info(p->an, p->cfg, p->index_bits, kernel_code(p->an, p->x_vec, p->y_vec), info);
   return FAMLIES_OK;
 }

@@ -5,7 +5,8 @@
 // (labels, grouping, orientation, indexing vectors), then cuts all problems
 // into (problem, tile) work items and deals them to a fixed grid of
 // workgroups: problems are spread over the XCDs by estimated cost (so a
-// problem's tiles share one L2), and each XCD's items form one queue,
+// problem's tiles share one L2; a problem larger than a quarter of an XCD's
+// share is cut into runs of tiles first), and each XCD's items form one queue,
 // largest problems first with a problem's tiles consecutive.  The
 // workgroups of an XCD take items from its queue with an atomic counter, so
 // a problem's tiles run side by side and no workgroup idles while its queue
@@ -60,14 +61,41 @@ struct BatchArgs {
   double alpha, beta;
 };
 
-// Tile classes of the batched kernel (BM = BN; BK fixed per element type).
-constexpr int kBatchClasses = 2;
-__host__ __device__ constexpr int batch_class_tile(int cls) { return cls == 0 ? 64 : 128; }
+// Tile classes of the batched kernel: BM x BN with BM, BN in {64, 128}
+// (bit 0 of the class: BM = 128, bit 1: BN = 128); BK fixed per element type.
+constexpr int kBatchClasses = 4;
+__host__ __device__ constexpr int batch_class_bm(int cls) { return (cls & 1) ? 128 : 64; }
+__host__ __device__ constexpr int batch_class_bn(int cls) { return (cls & 2) ? 128 : 64; }
 
-template <typename T, int BT, bool XK, bool YK>
+template <typename T, int BM, int BN, bool XK, bool YK>
 __device__ __forceinline__ void run_item(const TileJob<uint32_t>& j, T* smem) {
   constexpr int BK = sizeof(T) == 8 ? 16 : 32;
-  PlainTile<T, BT, BT, BK, XK ? kKGather : kRowGather, YK ? kKGather : kRowGather>::template run<uint32_t>(j, smem);
+  constexpr int kDepth = 1;
+  PlainTile<T, BM, BN, BK, XK ? kKGather : kRowGather, YK ? kKGather : kRowGather, kDepth>::template run<uint32_t>(j,
+                                                                                                               smem);
+}
+
+// One item of class (BM, BN); xy: bit 0 X gathered along K, bit 1 Y along K.
+template <typename T, int BM, int BN>
+__device__ __forceinline__ void run_class(int xy, const TileJob<uint32_t>& j, T* smem) {
+  switch (xy) {
+    case 0: run_item<T, BM, BN, false, false>(j, smem); break;
+    case 1: run_item<T, BM, BN, true, false>(j, smem); break;
+    case 2: run_item<T, BM, BN, false, true>(j, smem); break;
+    default: run_item<T, BM, BN, true, true>(j, smem); break;
+  }
+}
+
+// Wave-uniform copies (readfirstlane) of values every lane holds alike.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ P* uniform(P* p) {
+  return reinterpret_cast<P*>(uniform(reinterpret_cast<int64_t>(p)));
 }
 
 template <typename T>
@@ -81,45 +109,46 @@ __global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(a.counters + q, 1);
     __syncthreads();
-    const int it = next;
+    const int it = uniform(next);
     if (it >= count) break;  // the counter only grows: every workgroup gets here
+    // The item and its problem are the same for the whole workgroup: taking
+    // every field through readfirstlane keeps the tile's addresses and sizes
+    // in scalar registers (vector loads of them would hold ~70 VGPRs per
+    // lane through the tile and push the kernel into spills).
     const BatchItem item = a.items[beg + it];
-    const BatchProblemDev& P = a.probs[item.prob];
-    const int flags = P.flags;
+    const int prob = uniform(item.prob);
+    const BatchProblemDev& P = a.probs[prob];
+    const int flags = uniform(P.flags);
     const bool swapped = flags & 1;
     const int cls = flags >> 8;
-    const int bt = cls == 0 ? 64 : 128;
-    const uint32_t* o = a.pool + P.off;
+    const uint32_t* o = uniform(a.pool + P.off);
     TileJob<uint32_t> j;
-    j.x = static_cast<const T*>(swapped ? a.B[item.prob] : a.A[item.prob]) + P.xlo;
-    j.y = static_cast<const T*>(swapped ? a.A[item.prob] : a.B[item.prob]) + P.ylo;
-    j.c = static_cast<T*>(a.C[item.prob]) + P.clo;
-    j.xmn = o + P.pos[0];
-    j.xk = o + P.pos[1];
-    j.yk = o + P.pos[2];
-    j.ymn = o + P.pos[3];
-    j.cm = o + P.pos[4];
-    j.cn = o + P.pos[5];
-    j.M = P.M;
-    j.N = P.N;
-    j.m0 = item.tm * bt;
-    j.n0 = item.tn * bt;
+    j.x = uniform(static_cast<const T*>(swapped ? a.B[prob] : a.A[prob]) + P.xlo);
+    j.y = uniform(static_cast<const T*>(swapped ? a.A[prob] : a.B[prob]) + P.ylo);
+    j.c = uniform(static_cast<T*>(a.C[prob]) + P.clo);
+    j.xmn = o + uniform(P.pos[0]);
+    j.xk = o + uniform(P.pos[1]);
+    j.yk = o + uniform(P.pos[2]);
+    j.ymn = o + uniform(P.pos[3]);
+    j.cm = o + uniform(P.pos[4]);
+    j.cn = o + uniform(P.pos[5]);
+    j.M = uniform(P.M);
+    j.N = uniform(P.N);
+    j.m0 = uniform((int)item.tm) * batch_class_bm(cls);
+    j.n0 = uniform((int)item.tn) * batch_class_bn(cls);
     j.kbeg = 0;
-    j.kend = P.K;
+    j.kend = uniform(P.K);
     j.alpha = a.alpha;
     j.beta = a.beta;
     j.work = nullptr;
     j.ldw = 0;
     j.x_nkb = j.y_nkb = 0;
-    switch (((flags >> 1) & 3) | (cls << 2)) {
-      case 0: run_item<T, 64, false, false>(j, smem); break;
-      case 1: run_item<T, 64, true, false>(j, smem); break;
-      case 2: run_item<T, 64, false, true>(j, smem); break;
-      case 3: run_item<T, 64, true, true>(j, smem); break;
-      case 4: run_item<T, 128, false, false>(j, smem); break;
-      case 5: run_item<T, 128, true, false>(j, smem); break;
-      case 6: run_item<T, 128, false, true>(j, smem); break;
-      default: run_item<T, 128, true, true>(j, smem); break;
+    const int xy = (flags >> 1) & 3;
+    switch (cls) {
+      case 0: run_class<T, 64, 64>(xy, j, smem); break;
+      case 1: run_class<T, 128, 64>(xy, j, smem); break;
+      case 2: run_class<T, 64, 128>(xy, j, smem); break;
+      default: run_class<T, 128, 128>(xy, j, smem); break;
     }
     __syncthreads();
   }
@@ -140,6 +169,7 @@ struct BatchPlan {
   int64_t n_items = 0;
   double flops = 0.0;
   std::vector<int> scale_only;  // problems with K == 0 (alpha*A.B vanishes)
+  std::vector<int8_t> cls;      // tile class per problem, -1 when it has no tiles
   const int32_t* scale_dev = nullptr;
   ~BatchPlan() {
     if (d_buf) (void)hipFree(d_buf);
@@ -147,6 +177,12 @@ struct BatchPlan {
 };
 
 void destroy_batch(BatchPlan* b) { delete b; }
+
+void batch_info(const BatchPlan* b, famlies_plan_info* info) {
+  std::memset(info, 0, sizeof *info);
+  info->batch = b->n;
+  info->flops = b->flops;
+}
 
 // Problems whose product term vanishes (K == 0, or every problem when
 // alpha == 0): C = beta * C (beta == 0 writes zeros without reading C).  One
@@ -169,26 +205,22 @@ __global__ __launch_bounds__(kThreads) void batch_scale(BatchArgs a, const int32
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+int batch_class_of(int bm, int bn) { return (bm >= 128 ? 1 : 0) | (bn >= 128 ? 2 : 0); }
+
 // Tile class for a problem: the tile table's batched entry for its size class
-// if present, else the larger tile when both M and N fill it.
-static int pick_class(const famlies_handle_s* h, int dtype, const Analysis& an) {
+// if present, else 128 along each of M and N that fills it, 64 otherwise.
+static int pick_class(const famlies_handle_s* h, int dtype, const Analysis& an, bool* from_table) {
   TileCfg t;
-  if (h->table.lookup_batch(dtype, an.M, an.N, an.K, &t)) return t.bm >= 128 ? 1 : 0;
-  return (an.M >= 128 && an.N >= 128) ? 1 : 0;
+  *from_table = h->table.lookup_batch(dtype, an.M, an.N, an.K, &t);
+  if (*from_table) return batch_class_of(t.bm, t.bn);
+  return batch_class_of(an.M >= 128 ? 128 : 64, an.N >= 128 ? 128 : 64);
 }
 
-}  // namespace famlies
-
-using namespace famlies;
-
-extern "C" {
-
-static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
-                                      const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
-  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: null output pointer");
+famlies_status batch_plan_make(famlies_handle_s* h, famlies_plan_s** out, int dtype, int64_t n,
+                               const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                               int force_cls) {
   *out = nullptr;
-  famlies_handle_s* h = handle_of(htok);
-  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: invalid handle");
+  if (force_cls >= kBatchClasses) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: bad tile class");
   if (n < 0 || (n > 0 && (!A || !B || !C))) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: bad arrays");
   if (n > (1 << 30)) return fail(FAMLIES_ERR_UNSUPPORTED, "famlies_batch_plan: too many problems");
   auto* bp = new (std::nothrow) BatchPlan();
@@ -196,6 +228,7 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
   bp->dtype = dtype;
   bp->n = n;
   std::vector<BatchProblemDev> probs((size_t)n);
+  bp->cls.assign((size_t)n, -1);
   std::vector<uint32_t> pool;
   std::vector<int64_t> tmp;
   struct Job {
@@ -205,6 +238,7 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
   };
   std::vector<std::vector<Job>> per_prob((size_t)n);
   std::vector<double> prob_cost((size_t)n, 0.0);
+  int64_t table_hits = 0;
   const int BK = dtype == FAMLIES_F64 ? 16 : 32;
   for (int64_t p = 0; p < n; ++p) {
     Analysis an;
@@ -224,8 +258,10 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
       delete bp;
       return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": too large for the batched kernel");
     }
-    const int cls = pick_class(h, dtype, an);
-    const int bt = batch_class_tile(cls);
+    bool hit = false;
+    const int cls = force_cls >= 0 ? force_cls : pick_class(h, dtype, an, &hit);
+    table_hits += hit ? 1 : 0;
+    const int bm = batch_class_bm(cls), bn = batch_class_bn(cls);
     BatchProblemDev& d = probs[(size_t)p];
     d.M = (int32_t)an.M;
     d.N = (int32_t)an.N;
@@ -236,7 +272,7 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
     d.ylo = an.y_lo;
     d.clo = an.c_lo_mn;
     if (an.M == 0 || an.N == 0) continue;  // nothing to write
-    const int64_t mp = cdiv(an.M, bt) * bt, np = cdiv(an.N, bt) * bt;
+    const int64_t mp = cdiv(an.M, bm) * bm, np = cdiv(an.N, bn) * bn;
     const int64_t kp = cdiv(std::max<int64_t>(an.K, 1), BK) * BK + BK;
     const std::vector<Mode>* groups[6] = {&an.I, &an.P, &an.P, &an.J, &an.I, &an.J};
     const int which[6] = {0, 0, 1, 1, 2, 2};
@@ -265,13 +301,14 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
       continue;
     }
     bp->flops += 2.0 * (double)an.M * (double)an.N * (double)an.K;
-    const int tm = (int)cdiv(an.M, bt), tn = (int)cdiv(an.N, bt);
+    bp->cls[(size_t)p] = (int8_t)cls;
+    const int tm = (int)cdiv(an.M, bm), tn = (int)cdiv(an.N, bn);
     if (tm > 32767 || tn > 32767) {
       delete bp;
       return fail(FAMLIES_ERR_UNSUPPORTED, "problem " + std::to_string(p) + ": more than 32767 tiles along M or N");
     }
     // cost model: MFMA work of the padded tile plus a fixed per-item overhead
-    const double c = (double)bt * bt * (double)(cdiv(an.K, BK) * BK) + 64.0 * bt * bt;
+    const double c = (double)bm * bn * (double)(cdiv(an.K, BK) * BK) + 64.0 * bm * bn;
     for (int jn = 0; jn < tn; ++jn)
       for (int jm = 0; jm < tm; ++jm) per_prob[(size_t)p].push_back({(int32_t)p, (int16_t)jm, (int16_t)jn, c});
     prob_cost[(size_t)p] = c * tm * tn;
@@ -292,18 +329,38 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
     if (oe != hipSuccess || per_cu < 1) per_cu = 1;
   }
   const int grid = std::max(kXcds, (per_cu * h->num_cus) / kXcds * kXcds);
-  // 1) problems -> XCDs, largest first, to the least-loaded XCD
-  std::vector<int64_t> order((size_t)n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t a, int64_t b) { return prob_cost[(size_t)a] > prob_cost[(size_t)b]; });
+  // 1) problems -> XCDs, largest first, to the least-loaded XCD.  A problem
+  //    costing more than a quarter of an XCD's fair share is first cut into
+  //    runs of consecutive tiles (tiles of one Y panel stay together), each
+  //    placed on its own: a batch of a few large problems then still spreads
+  //    over every XCD.
+  double total_cost = 0.0;
+  for (double c : prob_cost) total_cost += c;
+  const double unit_cap = total_cost / (4.0 * kXcds);
+  struct Unit {
+    int64_t prob;
+    size_t first, count;
+    double cost;
+  };
+  std::vector<Unit> units;
+  for (int64_t p = 0; p < n; ++p) {
+    const auto& js = per_prob[(size_t)p];
+    if (js.empty()) continue;
+    const double c = prob_cost[(size_t)p];
+    const size_t parts = c > unit_cap ? std::min(js.size(), (size_t)std::ceil(c / unit_cap)) : 1;
+    for (size_t u = 0; u < parts; ++u) {
+      const size_t a0 = js.size() * u / parts, a1 = js.size() * (u + 1) / parts;
+      units.push_back({p, a0, a1 - a0, c * (double)(a1 - a0) / (double)js.size()});
+    }
+  }
+  std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
   std::vector<double> xload(kXcds, 0.0);
   std::vector<std::vector<Job>> xjobs(kXcds);
-  for (int64_t p : order) {
-    if (per_prob[(size_t)p].empty()) continue;
+  for (const Unit& u : units) {
     int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
-    xload[(size_t)x] += prob_cost[(size_t)p];
-    for (const Job& jb : per_prob[(size_t)p]) xjobs[(size_t)x].push_back(jb);
+    xload[(size_t)x] += u.cost;
+    const auto& js = per_prob[(size_t)u.prob];
+    for (size_t i = u.first; i < u.first + u.count; ++i) xjobs[(size_t)x].push_back(js[i]);
   }
   // 2) each XCD's queue: largest problems first, a problem's tiles
   //    consecutive, so the workgroups that draw them run them side by side
@@ -373,26 +430,17 @@ static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, in
   p->an.esize = dtype == FAMLIES_F64 ? 8 : 4;
   p->batch = bp;
   if (log_enabled())
-    std::fprintf(stderr, "[famlies] batch plan %s: %lld problems, %lld (problem, tile) items, grid %d, %zu K = 0\n",
+    std::fprintf(stderr,
+                 "[famlies] batch plan %s: %lld problems, %lld (problem, tile) items, grid %d, %zu K = 0, "
+                 "tile class from the table for %lld\n",
                  dtype == FAMLIES_F64 ? "f64" : "f32", (long long)n, (long long)bp->n_items, bp->grid,
-                 bp->scale_only.size());
-  void* tok = registry_add(p, ObjKind::kPlan);
-  if (!tok) {
-    destroy_plan(p);
-    return fail(FAMLIES_ERR_ALLOC, "famlies_batch_plan: no free object slot");
-  }
-  *out = static_cast<famlies_plan>(tok);
+                 bp->scale_only.size(), (long long)table_hits);
+  *out = p;
   return FAMLIES_OK;
 }
 
-famlies_status famlies_batch_plan(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
-                                  const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
-  return no_throw("famlies_batch_plan", [&] { return batch_plan_impl(htok, out, dtype, n, A, B, C); });
-}
-
-famlies_status famlies_batch_execute(famlies_plan tok, double alpha, double beta, const void* const* A_dev,
-                                     const void* const* B_dev, void* const* C_dev, void* stream) {
-  famlies_plan_s* p = plan_of(tok);
+famlies_status batch_execute_impl(famlies_plan_s* p, double alpha, double beta, const void* const* A_dev,
+                                  const void* const* B_dev, void* const* C_dev, void* stream) {
   if (!p || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: not a batched plan");
   BatchPlan* bp = p->batch;
   if (bp->n == 0) return FAMLIES_OK;
@@ -431,6 +479,55 @@ famlies_status famlies_batch_execute(famlies_plan tok, double alpha, double beta
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
   return FAMLIES_OK;
+}
+
+}  // namespace famlies
+
+using namespace famlies;
+
+extern "C" {
+
+static famlies_status batch_plan_impl(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
+                                      const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
+  if (!out) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: null output pointer");
+  *out = nullptr;
+  famlies_handle_s* h = handle_of(htok);
+  if (!h) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan: invalid handle");
+  famlies_plan_s* p = nullptr;
+  famlies_status st = batch_plan_make(h, &p, dtype, n, A, B, C, -1);
+  if (st != FAMLIES_OK) return st;
+  void* tok = registry_add(p, ObjKind::kPlan);
+  if (!tok) {
+    destroy_plan(p);
+    return fail(FAMLIES_ERR_ALLOC, "famlies_batch_plan: no free object slot");
+  }
+  *out = static_cast<famlies_plan>(tok);
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_batch_plan(famlies_handle htok, famlies_plan* out, int dtype, int64_t n,
+                                  const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C) {
+  return no_throw("famlies_batch_plan", [&] { return batch_plan_impl(htok, out, dtype, n, A, B, C); });
+}
+
+famlies_status famlies_batch_plan_tiles(famlies_plan tok, int32_t* tile_m, int32_t* tile_n, int64_t n) {
+  famlies_plan_s* p = plan_of(tok);
+  if (!p || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan_tiles: not a batched plan");
+  if (!tile_m || !tile_n || n != p->batch->n)
+    return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_plan_tiles: bad arrays or count");
+  for (int64_t i = 0; i < n; ++i) {
+    const int c = p->batch->cls[(size_t)i];
+    tile_m[i] = c < 0 ? 0 : batch_class_bm(c);
+    tile_n[i] = c < 0 ? 0 : batch_class_bn(c);
+  }
+  return FAMLIES_OK;
+}
+
+famlies_status famlies_batch_execute(famlies_plan tok, double alpha, double beta, const void* const* A_dev,
+                                     const void* const* B_dev, void* const* C_dev, void* stream) {
+  famlies_plan_s* p = plan_of(tok);
+  if (!p || !p->batch) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_batch_execute: not a batched plan");
+  return batch_execute_impl(p, alpha, beta, A_dev, B_dev, C_dev, stream);
 }
 
 }  // extern "C"

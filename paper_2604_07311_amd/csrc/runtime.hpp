@@ -37,6 +37,8 @@ struct TileTable {
 
 struct BatchPlan;
 void destroy_batch(BatchPlan* b);
+// famlies_plan_get_info of a batched plan: batch = problems, flops = total.
+void batch_info(const BatchPlan* b, famlies_plan_info* info);
 
 }  // namespace famlies
 
@@ -150,6 +152,17 @@ void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int
 // The nine indexing vectors, unpadded: X rows, X k, Y k, Y cols, C rows,
 // C cols, batch offsets of X, Y, C.
 void all_offsets(const Analysis& an, std::vector<int64_t>* v);
+// Plan a batch of n contractions for the persistent batched kernel;
+// force_cls >= 0 gives every problem that tile class (0: 64 x 64, 1: 128 x 64,
+// 2: 64 x 128, 3: 128 x 128), -1 takes it from the tile table or the default
+// rule.  The plan is not registered.
+famlies_status batch_plan_make(famlies_handle_s* h, famlies_plan_s** out, int dtype, int64_t n,
+                               const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
+                               int force_cls);
+famlies_status batch_execute_impl(famlies_plan_s* p, double alpha, double beta, const void* const* A_dev,
+                                  const void* const* B_dev, void* const* C_dev, void* stream);
+// Tile class of the batched kernel with tile BM x BN (each 64 or 128).
+int batch_class_of(int bm, int bn);
 // Plan one contraction; `force` (may be null) overrides the tile choice.
 famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, int compute,
                          const famlies_tensor* A, const famlies_tensor* B, const famlies_tensor* C,
