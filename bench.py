@@ -638,6 +638,11 @@ def wl_batched(args):
     import oracle
     import synth
     n = args.batch
+    table = None
+    if args.tile_table != "none":
+        table = args.tile_table or os.path.join(os.path.dirname(fm.__file__), "tables", "batch_mi355x.txt")
+        fm.famlies_load_tune_table(fm.handle(0), table)
+        log("batched: tile classes from %s" % table)
     log("batched: planning %d problems" % n)
     probs = synth.batched(n, seed=5)
     # read-only operands alias into one shared pool; outputs are disjoint
@@ -662,6 +667,7 @@ def wl_batched(args):
                                  [fm.make_desc(p.b.extents, p.b.strides, p.lb) for p in probs],
                                  [fm.make_desc(p.c.extents, p.c.strides, p.lc) for p in probs])
     plan_s = time.perf_counter() - t0
+    tiles = fm.famlies_batch_plan_tiles(plan, n)
     flops = sum(2.0 * np.prod(synth.sizes(p)) for p in probs)
     stream = torch.cuda.Stream()
 
@@ -696,7 +702,13 @@ def wl_batched(args):
     ms, launch_ms, _ = Timer(torch.cuda.current_stream()).run(g.replay, args.steps, args.warmup)
     out = base_record(args, flops / (ms * 1e-3) / 1e9, ms, "f32",
                       {"workload": "batched_%d_random_4index" % n, "problems": n,
-                       "dims": "U{4..48}", "launch": "one persistent kernel, graph replay"})
+                       "dims": "U{4..48}", "launch": "one persistent kernel, graph replay",
+                       "tile_table": os.path.basename(table) if table else None})
+    classes = {}
+    for t in tiles:
+        if t != (0, 0):
+            classes["%dx%d" % t] = classes.get("%dx%d" % t, 0) + 1
+    out["tile_classes"] = classes
     out["pct_mfma_peak"] = round(100 * flops / (ms * 1e-3) / PEAK["f32"], 2)
     out["plan_s"] = round(plan_s, 3)
     out["error_vs_fp64"] = {"problems_checked_fully": checked, "max_abs_err_over_D": worst}
@@ -720,6 +732,9 @@ def main():
     ap.add_argument("--o", type=int, default=32)
     ap.add_argument("--batch", type=int, default=20000)
     ap.add_argument("--only", choices=["f64", "f32"], default=None)
+    ap.add_argument("--tile-table", default="",
+                    help="batched: tile table to load (default: the package's measured MI355X table; "
+                         "'none': the built-in rule)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-int8", action="store_true",
                     help="ladder: skip FP64 emulated on INT8 MFMA reported under 'secondary'")

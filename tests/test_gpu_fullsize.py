@@ -134,10 +134,14 @@ def test_ladder_v192_o48_64bit(dtype, compute):
 
 def test_batched_20000():
     """The benchmark's batch: read-only operands in one shared pool, disjoint
-    outputs, one launch.  Every problem is checked on 8 sampled entries, 20
+    outputs, one launch, tile classes from the package's measured table (as
+    bench.py runs it).  Every problem is checked on 8 sampled entries, 20
     problems in full."""
+    import os
     import torch
     import paper_2604_07311_amd as fm
+    h = fm.famlies_create(0)
+    fm.famlies_load_tune_table(h, os.path.join(os.path.dirname(fm.__file__), "tables", "batch_mi355x.txt"))
     n = 20000
     probs = synth.batched(n, seed=5)
     pool_n = max(max(p.a.size for p in probs), max(p.b.size for p in probs)) * 8
@@ -154,14 +158,17 @@ def test_batched_20000():
     pa = ptr(pool.data_ptr(), aoff, [p.a for p in probs])
     pb = ptr(pool.data_ptr(), boff, [p.b for p in probs])
     pc = ptr(C.data_ptr(), coff[:-1], [p.c for p in probs])
-    plan = fm.famlies_batch_plan(fm.handle(0), fm.FAMLIES_F32,
+    plan = fm.famlies_batch_plan(h, fm.FAMLIES_F32,
                                  [fm.make_desc(p.a.extents, p.a.strides, p.la) for p in probs],
                                  [fm.make_desc(p.b.extents, p.b.strides, p.lb) for p in probs],
                                  [fm.make_desc(p.c.extents, p.c.strides, p.lc) for p in probs])
+    classes = {t for t in fm.famlies_batch_plan_tiles(plan, n) if t != (0, 0)}
+    print("tile classes in use: %s" % sorted(classes), flush=True)
     fm.famlies_batch_execute(plan, 1.0, 0.5, pa.data_ptr(), pb.data_ptr(), pc.data_ptr(),
                              torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     fm.famlies_plan_destroy(plan)
+    fm.famlies_destroy(h)
     pool_h = pool.cpu().numpy().astype(np.float64)
     C_h, C0_h = C.cpu().numpy().astype(np.float64), C0.cpu().numpy().astype(np.float64)
     worst = 0.0
