@@ -146,13 +146,16 @@ typedef struct {
   int32_t n_trace, n_diag;  /* labels summed inside one input; labels repeated in an input */
   int32_t tile_m, tile_n, tile_k;
   int32_t split_k;          /* number of K slices (1 = none) */
-  int32_t index_bits;       /* 32 or 64: width of the indexing vectors */
+  int32_t index_bits;       /* 32 or 64: width of the indexing vectors (32: every operand spans
+                               under 4 GiB -- byte offsets -- or under 2^31 elements -- element
+                               offsets, see index_elements; 64: element offsets) */
   int32_t kernel;           /* 1 plain, 3 bf16x3, 4 bf16x6 (1 + bf16 parts per operand), 8 + s FP64 on INT8 with s
                                slices; +16 / +32 when the kernel reads X / Y from affine unit-stride K blocks with
                                16-byte loads (block strides) */
   int32_t split_tiles;      /* split_k > 1: how many tiles run as K slices (the last ones in
                                tile order; the others run whole first); 0 without split-K */
   double flops;             /* 2*batch*m*n*k */
+  int32_t index_elements;   /* 1 when the indexing vectors count elements, 0 when bytes */
 } famlies_plan_info;
 
 /* Create a handle bound to HIP device `device` (reads the tile table named by
@@ -235,8 +238,8 @@ famlies_status famlies_batch_execute(famlies_plan p, double alpha, double beta,
  * split into bf16 parts -- so that famlies_execute_packed copies whole tiles
  * instead of gathering and splitting.  dst must hold famlies_pack_size bytes
  * and be 16-byte aligned; it is owned by the caller and valid for this plan
- * only.  UNSUPPORTED for plans whose offsets need 64 bits (an operand
- * spanning 4 GiB or more).  Asynchronous on `stream`. */
+ * only.  UNSUPPORTED for plans whose offsets are not byte offsets (an
+ * operand spanning 4 GiB or more).  Asynchronous on `stream`. */
 famlies_status famlies_pack_size(famlies_plan p, int operand, size_t *bytes);
 famlies_status famlies_pack(famlies_plan p, int operand, const void *src, void *dst, void *stream);
 /* As famlies_execute, where bit 0 of `packed` says A points to a buffer
@@ -296,7 +299,8 @@ famlies_status famlies_tune(famlies_handle h, const char *table_path, int flags)
  *   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits> [<split tiles>]]
  * A plan takes the entry of its size class (or the nearest one within two
  * classes).  The optional index bits 64 makes such plans use 64-bit indexing
- * vectors even when 32 bits reach every element (0: automatic).  The optional
+ * vectors even when 32 bits reach every element, e32 makes them use 32-bit
+ * element offsets wherever those reach (0 or 32: automatic).  The optional
  * split tiles n > 0 (plain FP64/FP32 plans with split > 1) cuts only the last
  * n tiles in tile order into K slices; the others run over all of K first.
  * Errors: INVALID_ARG for an unreadable or malformed file (the handle's table

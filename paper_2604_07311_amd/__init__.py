@@ -75,7 +75,8 @@ class famlies_plan_info(ctypes.Structure):
                 ("n_diag", ctypes.c_int32), ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
                 ("tile_k", ctypes.c_int32), ("split_k", ctypes.c_int32),
                 ("index_bits", ctypes.c_int32), ("kernel", ctypes.c_int32),
-                ("split_tiles", ctypes.c_int32), ("flops", ctypes.c_double)]
+                ("split_tiles", ctypes.c_int32), ("flops", ctypes.c_double),
+                ("index_elements", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

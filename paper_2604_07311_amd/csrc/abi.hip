@@ -79,9 +79,11 @@ static famlies_status index_image(famlies_plan_s* p, int64_t mp, int64_t np, int
   offsets(an.Lm, 0, an.L, an.L, v[6]);
   offsets(an.Lm, 1, an.L, an.L, v[7]);
   offsets(an.Lm, 2, an.L, an.L, v[8]);
-  const bool bytes = sizeof(OffT) == 4;
+  // 32-bit forms rebase the row vectors to each operand's lowest element;
+  // the byte form also scales every offset to bytes
+  const bool rebase = sizeof(OffT) == 4, bytes = std::is_same<OffT, uint32_t>::value;
   const int64_t es = an.esize;
-  vec_flags(an, p->cfg.bk, bytes ? 32 : 64, v, &p->x_vec, &p->y_vec);
+  vec_flags(an, p->cfg.bk, sizeof(OffT) == 4 ? 32 : 64, v, &p->x_vec, &p->y_vec);
   const int64_t shift[6] = {an.x_lo, 0, 0, an.y_lo, an.c_lo_mn, 0};
   size_t n6 = 0;
   for (int i = 0; i < 6; ++i) n6 += v[i].size();
@@ -96,6 +98,8 @@ static famlies_status index_image(famlies_plan_s* p, int64_t mp, int64_t np, int
     for (int64_t x : v[i]) {
       if (bytes)
         o[pos++] = (OffT)(uint64_t)((x - shift[i]) * es);  // wraps modulo 2^32 on purpose
+      else if (rebase)
+        o[pos++] = (OffT)(x - shift[i]);  // |value| < 2^31 (index_form)
       else
         o[pos++] = (OffT)x;
     }
@@ -122,12 +126,12 @@ static PlainArgs<OffT> make_args(const famlies_plan_s* p, const void* x, const v
   PlainArgs<OffT> a;
   const OffT* o = static_cast<const OffT*>(p->d_off);
   const int64_t* lb = reinterpret_cast<const int64_t*>(static_cast<const char*>(p->d_off) + p->batch_off_bytes);
-  const bool bytes = sizeof(OffT) == 4;
+  const bool rebased = sizeof(OffT) == 4;
   const int64_t es = p->an.esize;
-  // in the byte form the kernel addresses each operand from its lowest element
-  a.x = x ? static_cast<const char*>(x) + (bytes ? p->an.x_lo * es : 0) : nullptr;
-  a.y = y ? static_cast<const char*>(y) + (bytes ? p->an.y_lo * es : 0) : nullptr;
-  a.c = static_cast<char*>(c) + (bytes ? p->an.c_lo_mn * es : 0);
+  // in the 32-bit forms the kernel addresses each operand from its lowest element
+  a.x = x ? static_cast<const char*>(x) + (rebased ? p->an.x_lo * es : 0) : nullptr;
+  a.y = y ? static_cast<const char*>(y) + (rebased ? p->an.y_lo * es : 0) : nullptr;
+  a.c = static_cast<char*>(c) + (rebased ? p->an.c_lo_mn * es : 0);
   a.xmn = o + p->off_pos[0];
   a.xk = o + p->off_pos[1];
   a.yk = o + p->off_pos[2];
@@ -173,7 +177,7 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
   const int i8 = int8_slices(compute);
   p->cfg = i8 ? int8_tile() : force ? *force : choose_tiles(h, an, &p->table_hit);
   if (i8 && force) p->cfg.index_bits = force->index_bits;
-  p->index_bits = p->cfg.index_bits == 64 ? 64 : index_bits_for(an);
+  index_form(an, p->cfg.index_bits, &p->index_bits, &p->elem32);
   const int ns = split_parts(compute);
   if (i8) {
     // fixed tile (int8_tile): no split-K, no tile table
@@ -218,8 +222,9 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
   const int64_t mp = ceil_div(std::max<int64_t>(an.M, 1), p->cfg.bm) * p->cfg.bm;
   const int64_t np = ceil_div(std::max<int64_t>(an.N, 1), p->cfg.bn) * p->cfg.bn;
   const int64_t kp = ceil_div(std::max<int64_t>(an.K, 1), p->cfg.bk) * p->cfg.bk + p->cfg.bk;
-  st = p->index_bits == 32 ? index_image<uint32_t>(p, mp, np, kp, image)
-                           : index_image<int64_t>(p, mp, np, kp, image);
+  st = p->index_bits == 64 ? index_image<int64_t>(p, mp, np, kp, image)
+       : p->elem32          ? index_image<int32_t>(p, mp, np, kp, image)
+                            : index_image<uint32_t>(p, mp, np, kp, image);
   if (st != FAMLIES_OK) return st;
   if (i8 && an.K > 0) {
     p->work_bytes = int8_work_bytes(i8, an.M, an.N, an.K, an.L);  // digit planes and exponents
@@ -269,7 +274,8 @@ famlies_status make_plan(famlies_handle h, famlies_plan* out, int dtype, int com
 }
 
 void log_plan(const famlies_plan_s* p) {
-  log_decision("plan", p->an, p->cfg, p->index_bits, p->x_vec, p->y_vec, p->work_bytes, p->table_hit);
+  log_decision("plan", p->an, p->cfg, p->elem32 ? -32 : p->index_bits, p->x_vec, p->y_vec, p->work_bytes,
+               p->table_hit);
 }
 
 void destroy_plan(famlies_plan_s* p) {
@@ -373,6 +379,7 @@ famlies_status famlies_plan_get_info(famlies_plan tok, famlies_plan_info* info) 
     return FAMLIES_OK;
   }
   fill_info(p->an, p->cfg, p->index_bits, kernel_code(p->an, p->x_vec, p->y_vec), info);
+  info->index_elements = p->index_bits == 64 || p->elem32;
   return FAMLIES_OK;
 }
 
@@ -443,7 +450,9 @@ famlies_status execute_impl(famlies_plan_s* p, double alpha, const void* A, cons
     e = p->index_bits == 32 ? launch_int8(make_args<uint32_t>(p, x, y, C, alpha, beta), i8, xmode, ymode, s)
                             : launch_int8(make_args<int64_t>(p, x, y, C, alpha, beta), i8, xmode, ymode, s);
   } else if (ns && L.kind == PlainLaunch::kMain) {
-    if (p->index_bits == 32) {
+    if (p->elem32) {
+      e = launch_split(make_args<int32_t>(p, x, y, C, alpha, beta), L, ns, s);
+    } else if (p->index_bits == 32) {
       PlainArgs<uint32_t> a = make_args<uint32_t>(p, x, y, C, alpha, beta);
       if (xp) {  // the packed buffer is addressed from its start, not through offsets
         a.x = x;
@@ -457,6 +466,8 @@ famlies_status execute_impl(famlies_plan_s* p, double alpha, const void* A, cons
     } else {
       e = launch_split(make_args<int64_t>(p, x, y, C, alpha, beta), L, ns, s);
     }
+  } else if (p->elem32) {
+    e = launch_plain(an.dtype, make_args<int32_t>(p, x, y, C, alpha, beta), L, s);
   } else if (p->index_bits == 32) {
     PlainArgs<uint32_t> a = make_args<uint32_t>(p, x, y, C, alpha, beta);
     if (xp) {

@@ -34,16 +34,26 @@ __device__ __forceinline__ int xcd_remap(int bid, int total) {
 }
 
 // Element at `off` from `base`: uint32_t offsets count bytes (an SGPR base
-// plus a 32-bit VGPR offset per load), int64_t offsets count elements.
+// plus a 32-bit VGPR offset per load); int32_t and int64_t offsets count
+// elements (int32_t for operands past 4 GiB but under 2^31 elements: 32-bit
+// registers per offset like the byte form).
 template <typename T>
 __device__ __forceinline__ T* at(T* base, uint32_t off) {
   typedef typename std::conditional<std::is_const<T>::value, const char, char>::type byte;
   return reinterpret_cast<T*>(reinterpret_cast<byte*>(base) + off);
 }
 template <typename T>
+__device__ __forceinline__ T* at(T* base, int32_t off) {
+  return base + (int64_t)off;
+}
+template <typename T>
 __device__ __forceinline__ T* at(T* base, int64_t off) {
   return base + off;
 }
+
+// Offsets that count bytes (the uint32_t form) rather than elements.
+template <typename OffT>
+constexpr bool kByteOffsets = std::is_same<OffT, uint32_t>::value;
 
 // Operands always live in global memory.  Loads and stores through these
 // helpers say so, so they compile to global (not flat) instructions even when
@@ -278,8 +288,8 @@ struct PackedGather {
 template <typename T, typename OffT, int BR, int BK, int NSLOT = 1>
 struct VecKGather {
   static constexpr int VK = 16 / (int)sizeof(T);
-  // one element in offset units: bytes for 32-bit offsets, elements for 64-bit ones
-  static constexpr int kStep = sizeof(OffT) == 4 ? (int)sizeof(T) : 1;
+  // one element in offset units: bytes for the byte form, else 1
+  static constexpr int kStep = kByteOffsets<OffT> ? (int)sizeof(T) : 1;
   static constexpr int LDK = BK + VK;
   static constexpr int KT = BK / VK;           // threads along k
   static constexpr int RSTEP = kThreads / KT;  // rows between a thread's runs

@@ -67,10 +67,15 @@ void offsets(const std::vector<Mode>& modes, int which, int64_t n, int64_t n_pad
              std::vector<int64_t>& out);
 
 // Tile configuration of the plain kernels.
+// TileCfg::index_bits value that asks for int32 element offsets.
+constexpr int kForceElem32 = 33;
+
 struct TileCfg {
   int bm = 128, bn = 128, bk = 16;
   int split = 1;
-  int index_bits = 0;  // 64: use 64-bit indexing vectors even where 32 bits reach (0: automatic)
+  // 0: automatic; 64: 64-bit indexing vectors even where 32 bits reach;
+  // kForceElem32: 32-bit element offsets wherever they reach
+  int index_bits = 0;
   // split > 1: how many tiles, the last ones in tile order, run as `split`
   // K slices each; the others run whole K first (0: every tile is split)
   int tail = 0;

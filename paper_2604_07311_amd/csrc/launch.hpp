@@ -15,6 +15,7 @@ struct PlainLaunch {
 };
 
 hipError_t launch_plain(int dtype, const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s);
+hipError_t launch_plain(int dtype, const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s);
 hipError_t launch_plain(int dtype, const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s);
 bool plain_tile_supported(int dtype, int bm, int bn, int bk);
 

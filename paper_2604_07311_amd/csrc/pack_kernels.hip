@@ -131,8 +131,8 @@ famlies_status pack_geom(famlies_plan_s* p, int operand, PackGeom* g) {
   g->bk = p->cfg.bk;
   const bool tile_ok = ns ? split_tile_supported(ns, p->cfg.bm, p->cfg.bn)
                           : plain_tile_supported(an.dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk);
-  if (!tile_ok || p->index_bits != 32)
-    return fail(FAMLIES_ERR_UNSUPPORTED, "pack: this plan's offsets need 64 bits (no packed kernel)");
+  if (!tile_ok || p->index_bits != 32 || p->elem32)
+    return fail(FAMLIES_ERR_UNSUPPORTED, "pack: an operand of this plan spans 4 GiB or more (no packed kernel)");
   if (an.M == 0 || an.N == 0 || an.K == 0) return fail(FAMLIES_ERR_UNSUPPORTED, "pack: empty problem");
   g->rows = g->x ? an.M : an.N;
   g->tiles = (g->rows + g->br - 1) / g->br;

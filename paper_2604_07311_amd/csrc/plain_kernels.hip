@@ -131,12 +131,10 @@ static void launch_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) {
   hipLaunchKernelGGL((plain_contract<T, OffT, BM, BN, BK, XM, YM>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered operands (modes 0, 1) with either offset width; pre-packed
-// operands (mode 2) with 32-bit offsets only.
+// Gathered and affine-block operands (modes 0, 1, 3) with every offset form;
+// pre-packed operands (mode 2) with byte offsets only.
 template <typename T, typename OffT, int BM, int BN, int BK>
 static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
-  // gathered and affine-block modes for every offset width; pre-packed
-  // operands with 32-bit offsets only
   const int code = xm * 4 + ym;
   switch (code) {
     case 0: launch_one<T, OffT, BM, BN, BK, 0, 0>(a, grid, s); return hipGetLastError();
@@ -150,7 +148,7 @@ static hipError_t launch_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid
     case 15: launch_one<T, OffT, BM, BN, BK, 3, 3>(a, grid, s); return hipGetLastError();
     default: break;
   }
-  if constexpr (sizeof(OffT) == 4) {
+  if constexpr (kByteOffsets<OffT>) {
     switch (code) {
       case 2: launch_one<T, OffT, BM, BN, BK, 0, 2>(a, grid, s); return hipGetLastError();
       case 6: launch_one<T, OffT, BM, BN, BK, 1, 2>(a, grid, s); return hipGetLastError();
@@ -191,6 +189,11 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
 hipError_t launch_plain(int dtype, const PlainArgs<uint32_t>& a, const PlainLaunch& L, hipStream_t s) {
   return dtype == FAMLIES_F64 ? launch_plain_t<double, uint32_t>(a, L, s)
                               : launch_plain_t<float, uint32_t>(a, L, s);
+}
+
+hipError_t launch_plain(int dtype, const PlainArgs<int32_t>& a, const PlainLaunch& L, hipStream_t s) {
+  return dtype == FAMLIES_F64 ? launch_plain_t<double, int32_t>(a, L, s)
+                              : launch_plain_t<float, int32_t>(a, L, s);
 }
 
 hipError_t launch_plain(int dtype, const PlainArgs<int64_t>& a, const PlainLaunch& L, hipStream_t s) {

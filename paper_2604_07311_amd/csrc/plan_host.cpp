@@ -155,6 +155,27 @@ int index_bits_for(const Analysis& an) {
   return ((an.x_span + 1) * es < lim && (an.y_span + 1) * es < lim && (an.c_span + 1) * es < lim) ? 32 : 64;
 }
 
+void index_form(const Analysis& an, int force, int* bits, bool* elem32) {
+  // int32 element offsets: rebased row offsets lie in [0, span] and K
+  // offsets in [-span, span], every sum in [0, span]: all below 2^31
+  const int64_t lim = ((int64_t)1 << 31) - 64;
+  const bool e32 = !int8_slices(an.compute) && an.x_span + 1 < lim && an.y_span + 1 < lim && an.c_span + 1 < lim;
+  *elem32 = false;
+  if (force == 64) {
+    *bits = 64;
+  } else if (force == kForceElem32 && e32) {
+    *bits = 32;
+    *elem32 = true;
+  } else if (index_bits_for(an) == 32) {
+    *bits = 32;
+  } else if (e32) {
+    *bits = 32;
+    *elem32 = true;
+  } else {
+    *bits = 64;
+  }
+}
+
 // Upload the indexing vectors (padded to the tile grid) into one device
 // buffer: six OffT vectors (X rows, X k, Y k, Y cols, C rows, C cols), then
 // the three int64 batch-offset vectors.  In the uint32 form every row vector
@@ -223,7 +244,8 @@ bool log_enabled() {
 }
 
 // One line on stderr: what the planner decided (orientation, loaders, tile,
-// split, index width, workspace).
+// split, index form -- index_bits 32: uint32 bytes, -32: int32 elements, 64:
+// int64 elements -- and workspace).
 void log_decision(const char* what, const Analysis& an, const TileCfg& cfg, int index_bits, bool x_vec,
                   bool y_vec, size_t work_bytes, bool table_hit) {
   static const char* loader[4] = {"rows", "k-gather", "packed", "k-affine"};
@@ -235,12 +257,13 @@ void log_decision(const char* what, const Analysis& an, const TileCfg& cfg, int 
                                                     : "native";
   std::fprintf(stderr,
                "[famlies] %s %s/%s M=%lld N=%lld K=%lld L=%lld swapped=%d groups=%zu/%zu/%zu/%zu "
-               "trace=%d diag=%d X=%s Y=%s tile=%dx%dx%d split=%d split_tiles=%d index_bits=%d "
+               "trace=%d diag=%d X=%s Y=%s tile=%dx%dx%d split=%d split_tiles=%d index=%s "
                "workspace=%zu B%s\n",
                what, an.dtype == FAMLIES_F64 ? "f64" : "f32", comp, (long long)an.M, (long long)an.N,
                (long long)an.K, (long long)an.L, an.swapped ? 1 : 0, an.I.size(), an.J.size(), an.P.size(),
                an.Lm.size(), an.n_trace, an.n_diag, loader[xm], loader[ym], cfg.bm, cfg.bn, cfg.bk, cfg.split,
-               cfg.split > 1 ? (cfg.tail ? cfg.tail : -1) : 0, index_bits, work_bytes,
+               cfg.split > 1 ? (cfg.tail ? cfg.tail : -1) : 0,
+               index_bits == 32 ? "u32-bytes" : index_bits == -32 ? "i32-elements" : "i64-elements", work_bytes,
                table_hit ? " (tile table)" : "");
 }
 
@@ -269,7 +292,9 @@ static famlies_status analyze_impl(int dtype, int compute, const famlies_tensor*
   }
   int kchunk = 0, head = 0;
   finalize_split(&t, an.K, ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn), &kchunk, &head);
-  const int ib = index_bits_for(an);
+  int ib = 64;
+  bool e32 = false;
+  index_form(an, 0, &ib, &e32);
   std::vector<int64_t> v[9];
   bool xv = false, yv = false;
   if (an.M > 0 && an.N > 0) {
@@ -277,7 +302,8 @@ static famlies_status analyze_impl(int dtype, int compute, const famlies_tensor*
     vec_flags(an, t.bk, ib, v, &xv, &yv);
   }
   fill_info(an, t, ib, kernel_code(an, xv, yv), info);
-  if (log_enabled()) log_decision("analyze", an, t, ib, xv, yv, 0, false);
+  info->index_elements = ib == 64 || e32;
+  if (log_enabled()) log_decision("analyze", an, t, e32 ? -32 : ib, xv, yv, 0, false);
   if (offs) {
     const int64_t need = 2 * an.M + 2 * an.K + 2 * an.N + 3 * an.L;
     if (offs_len < need) return fail(FAMLIES_ERR_INVALID_ARG, "famlies_analyze: offsets buffer too short");

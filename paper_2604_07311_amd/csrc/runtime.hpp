@@ -56,6 +56,7 @@ struct famlies_plan_s {
   famlies::Analysis an;
   famlies::TileCfg cfg;
   int index_bits = 32;
+  bool elem32 = false;     // index_bits 32: int32 element offsets (else uint32 byte offsets)
   int kchunk = 0;
   int head = 0;            // split-K plans: tiles computed whole before the split ones
   void* d_off = nullptr;   // six OffT indexing vectors, then three int64 batch vectors
@@ -146,6 +147,13 @@ TileCfg int8_tile();
 // 32: uint32 byte offsets from each operand's lowest element (every operand
 // spans less than 4 GiB over its non-batch modes); 64: int64 element offsets.
 int index_bits_for(const Analysis& an);
+// The indexing-vector form of a plan: *bits 32 with *elem32 false (uint32
+// byte offsets), 32 with *elem32 true (int32 element offsets from each
+// operand's lowest element: spans of 4 GiB and more but under 2^31
+// elements; not for INT8 plans, whose slicer reads bytes or int64), or 64
+// (int64 element offsets).  force: TileCfg::index_bits (0 automatic, 64, or
+// kForceElem32: int32 element offsets wherever they reach).
+void index_form(const Analysis& an, int force, int* bits, bool* elem32);
 // Affine-block flags of X and Y for a plan with K-slice depth bk; v holds
 // the nine indexing vectors in upload order.
 void vec_flags(const Analysis& an, int bk, int index_bits, const std::vector<int64_t>* v, bool* xv, bool* yv);
@@ -170,6 +178,7 @@ famlies_status make_plan(famlies_handle_s* h, famlies_plan_s** out, int dtype, i
 
 // Split-bf16 kernels: ns = 2 (bf16x3) or 3 (bf16x6) parts per operand.
 hipError_t launch_split(const PlainArgs<uint32_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
+hipError_t launch_split(const PlainArgs<int32_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
 hipError_t launch_split(const PlainArgs<int64_t>& a, const PlainLaunch& L, int ns, hipStream_t s);
 bool split_tile_supported(int ns, int bm, int bn);
 inline int split_parts(int compute) { return compute == FAMLIES_BF16X6 ? 3 : compute == FAMLIES_BF16X3 ? 2 : 0; }

@@ -429,8 +429,8 @@ static void launch_split_one(const PlainArgs<OffT>& a, int grid, hipStream_t s) 
   hipLaunchKernelGGL((split_contract<OffT, BM, BN, XM, YM, NS>), dim3(grid), dim3(kThreads), 0, s, a);
 }
 
-// Gathered and affine-block operands with either offset width; pre-packed
-// operands with 32-bit offsets only.
+// Gathered and affine-block operands with every offset form; pre-packed
+// operands with byte offsets only.
 template <typename OffT, int BM, int BN, int NS>
 static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, int grid, hipStream_t s) {
   const int code = xm * 4 + ym;
@@ -446,7 +446,7 @@ static hipError_t launch_split_tile(const PlainArgs<OffT>& a, int xm, int ym, in
     case 15: launch_split_one<OffT, BM, BN, NS, 3, 3>(a, grid, s); return hipGetLastError();
     default: break;
   }
-  if constexpr (sizeof(OffT) == 4) {
+  if constexpr (kByteOffsets<OffT>) {
     switch (code) {
       case 2: launch_split_one<OffT, BM, BN, NS, 0, 2>(a, grid, s); return hipGetLastError();
       case 6: launch_split_one<OffT, BM, BN, NS, 1, 2>(a, grid, s); return hipGetLastError();
@@ -486,6 +486,9 @@ static hipError_t launch_split_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
 }
 
 hipError_t launch_split(const PlainArgs<uint32_t>& a, const PlainLaunch& L, int ns, hipStream_t s) {
+  return launch_split_t(a, L, ns, s);
+}
+hipError_t launch_split(const PlainArgs<int32_t>& a, const PlainLaunch& L, int ns, hipStream_t s) {
   return launch_split_t(a, L, ns, s);
 }
 hipError_t launch_split(const PlainArgs<int64_t>& a, const PlainLaunch& L, int ns, hipStream_t s) {

@@ -51,7 +51,8 @@ void TileTable::put(const Entry& e) {
 // Format: '#' comments; one entry per line:
 //   <plain|batch> <dtype> <compute> <log2 M> <log2 N> <log2 K> <bm> <bn> <bk> <split> [<index bits> [<split tiles>]]
 // where the optional index bits 64 makes plans of that class use 64-bit
-// indexing vectors even when 32 bits reach every element (0: automatic), and
+// indexing vectors even when 32 bits reach every element, e32 makes them use
+// 32-bit element offsets wherever those reach (0 or 32: automatic), and
 // split tiles > 0 splits only that many tiles, the last in tile order (0:
 // every tile when split > 1).
 bool TileTable::load(const std::string& path, std::string* err) {
@@ -76,13 +77,13 @@ bool TileTable::load(const std::string& path, std::string* err) {
       *err = path + ":" + std::to_string(ln) + ": malformed entry";
       return false;
     }
-    int bits = 0;
+    std::string bits;
     if (is >> bits) {
-      if (bits != 0 && bits != 32 && bits != 64) {
-        *err = path + ":" + std::to_string(ln) + ": index bits must be 32 or 64";
+      if (bits != "0" && bits != "32" && bits != "64" && bits != "e32") {
+        *err = path + ":" + std::to_string(ln) + ": index bits must be 0, 32, 64 or e32";
         return false;
       }
-      e.cfg.index_bits = bits == 64 ? 64 : 0;
+      e.cfg.index_bits = bits == "64" ? 64 : bits == "e32" ? kForceElem32 : 0;
       int tail = 0;
       if (is >> tail) {
         if (tail < 0) {
@@ -110,7 +111,12 @@ bool TileTable::save(const std::string& path, std::string* err) const {
     f << (e.kind == 0 ? "plain" : "batch") << ' ' << e.dtype << ' ' << e.compute << ' ' << e.lm << ' '
       << e.ln << ' ' << e.lk << ' ' << e.cfg.bm << ' ' << e.cfg.bn << ' ' << e.cfg.bk << ' '
       << e.cfg.split;
-    if (e.cfg.index_bits || e.cfg.tail) f << ' ' << e.cfg.index_bits;
+    if (e.cfg.index_bits || e.cfg.tail) {
+      if (e.cfg.index_bits == kForceElem32)
+        f << " e32";
+      else
+        f << ' ' << e.cfg.index_bits;
+    }
     if (e.cfg.tail) f << ' ' << e.cfg.tail;
     f << '\n';
   }

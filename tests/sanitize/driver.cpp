@@ -61,11 +61,11 @@ static int run_analyze(const char* path) {
     st = famlies_analyze(dtype, compute, &T[0], &T[1], &T[2], &info, offs.data(), len);
     uint64_t sum = 0;
     for (int64_t i = 0; i < len; ++i) sum += (uint64_t)offs[(size_t)i] * (uint64_t)(i % 97 + 1);
-    std::printf("%d %lld %lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %llu\n", st,
+    std::printf("%d %lld %lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %llu\n", st,
                 (long long)info.m, (long long)info.n, (long long)info.k, (long long)info.batch, info.swapped,
                 info.x_kfast, info.y_kfast, info.n_i, info.n_j, info.n_p, info.n_batch, info.n_trace,
                 info.n_diag, info.tile_m, info.tile_n, info.tile_k, info.split_k, info.index_bits, info.kernel,
-                info.split_tiles, (unsigned long long)sum);
+                info.split_tiles, info.index_elements, (unsigned long long)sum);
   }
   return 0;
 }

@@ -315,6 +315,22 @@ def test_degenerate_shapes(fm):
     assert info["m"] == 0
 
 
+def test_index_forms(fm):
+    """Indexing-vector form by operand span: uint32 byte offsets below 4 GiB,
+    int32 element offsets from 4 GiB up to 2^31 elements (not for the INT8
+    modes), int64 element offsets beyond."""
+    def form(dtype, compute, m, k):
+        info, _ = fm.famlies_analyze(dtype, compute, fm.make_desc([m, k], [k, 1], "ik"),
+                                     fm.make_desc([k, 8], [1, k], "kj"), fm.make_desc([m, 8], [8, 1], "ij"))
+        return info["index_bits"], info["index_elements"]
+    assert form(fm.FAMLIES_F32, 0, 1 << 14, 1 << 14) == (32, 0)              # 1 GiB
+    assert form(fm.FAMLIES_F32, 0, 40000, 40000) == (32, 1)                  # 6.4 GB, 1.6e9 elements
+    assert form(fm.FAMLIES_F64, 0, 40000, 40000) == (32, 1)                  # 12.8 GB
+    assert form(fm.FAMLIES_F32, fm.FAMLIES_BF16X3, 40000, 40000) == (32, 1)
+    assert form(fm.FAMLIES_F64, fm.FAMLIES_INT8X6, 40000, 40000) == (64, 1)  # INT8: bytes or int64
+    assert form(fm.FAMLIES_F32, 0, 50000, 50000) == (64, 1)                  # 2.5e9 elements
+
+
 def test_no_gpu_means_loud_failure(fm):
     import torch
     if torch.cuda.is_available():

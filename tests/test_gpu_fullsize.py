@@ -4,7 +4,7 @@ oracle computed one by one (FP64, compensated), with the same bounds as the
 small-problem tests.  Workloads: the ladder v=128 o=32 in FP64, FP32 and
 bf16x3; the ring o=48 v=192 in FP32, bf16x3, bf16x6 and FP64 (the FP32 data,
 exact in FP64); the ladder v=192 o=48, whose operands span more than 4 GiB
-(64-bit indexing), in FP32, bf16x3, bf16x6 and FP64; and the 20,000-problem
+(element offsets), in FP32, bf16x3, bf16x6 and FP64; and the 20,000-problem
 batch."""
 import numpy as np
 import pytest
@@ -119,13 +119,15 @@ def test_ring_o48_v192(dtype, compute):
 
 @pytest.mark.parametrize("dtype,compute", [("f32", "native"), ("f32", "bf16x3"), ("f32", "bf16x6"),
                                            ("f64", "native")])
-def test_ladder_v192_o48_64bit(dtype, compute):
-    """W is 192^4 elements (5.4 GB in FP32, 10.9 GB in FP64): the plan needs
-    64-bit offsets."""
+def test_ladder_v192_o48_past_4gib(dtype, compute):
+    """W is 192^4 elements (5.4 GB in FP32, 10.9 GB in FP64): past the byte
+    offsets' 4 GiB, so the plan counts its offsets in elements."""
     p = _problem("ladder192")
     info, got = _run_single(p, dtype, compute)
-    note("ladder v192 o48 %s %s: bits %d kernel %d" % (dtype, compute, info["index_bits"], info["kernel"]))
-    assert info["index_bits"] == 64
+    note("ladder v192 o48 %s %s: bits %d elements %d kernel %d" % (dtype, compute, info["index_bits"],
+                                                                  info["index_elements"], info["kernel"]))
+    # 1.36e9 elements: past 4 GiB, under 2^31 elements -> 32-bit element offsets
+    assert info["index_bits"] == 32 and info["index_elements"] == 1
     want, d, dp, g = _sampled(p, got, 1024, 503)
     _check(compute, dtype, 192 * 192, g, want, d, dp)
     note("ladder v192 o48 %s %s normwise %.3e" % (dtype, compute,

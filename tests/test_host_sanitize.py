@@ -117,7 +117,7 @@ def _expected(fm, case):
         s = (s + (v % (1 << 64)) * (i % 97 + 1)) % (1 << 64)
     f = ["m", "n", "k", "batch", "swapped", "x_kfast", "y_kfast", "n_i", "n_j", "n_p", "n_batch",
          "n_trace", "n_diag", "tile_m", "tile_n", "tile_k", "split_k", "index_bits", "kernel",
-         "split_tiles"]
+         "split_tiles", "index_elements"]
     return " ".join(["0"] + [str(int(info[k])) for k in f] + [str(s)])
 
 
