@@ -187,10 +187,10 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
       p->cfg.split = 1;
       p->cfg.tail = 0;
     }
-    p->cfg.bk = 32;
+    p->cfg.bk = split_slice_k(ns);
     // bf16x3 on large problems: a 256 x 128 tile (128 x 64 per wave) halves
-    // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 has three
-    // accumulators per block and stays at 128 x 128).  It has registers for
+    // the LDS bytes per MFMA of the 128 x 128 tile (bf16x6 stays at 128 x 128
+    // with 16-deep slices, two workgroups per CU).  It has registers for
     // one slice in flight and one workgroup per CU, so it is taken only when
     // both operands are element-gathered along K: a row-gathered operand
     // keeps the 128 x 128 tile with two slices in flight (ring o=48 v=192:

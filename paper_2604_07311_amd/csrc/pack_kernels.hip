@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kThreads) void pack_plain(PackArgs<OffT> p) {
 
 template <typename OffT, int BR, int NS>
 __global__ __launch_bounds__(kThreads) void pack_split(PackArgs<OffT> p) {
-  constexpr int BK = 32;
+  constexpr int BK = split_slice_k(NS);
   const int64_t total = (int64_t)p.L * p.tiles * p.nkb * BR * BK;
   __bf16* dst = static_cast<__bf16*>(p.dst);
   for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < total; e += (int64_t)gridDim.x * kThreads) {
@@ -83,7 +83,7 @@ static hipError_t launch_pack_t(const PackArgs<OffT>& a, int dtype, int ns, int 
       hipLaunchKernelGGL((pack_plain<float, OffT, 64, 32>), dim3(grid), dim3(kThreads), 0, s, a);
     else
       return hipErrorInvalidValue;
-  } else if (bk != 32) {
+  } else if (bk != split_slice_k(ns)) {
     return hipErrorInvalidValue;
   } else if (ns == 2 && br == 256) {
     hipLaunchKernelGGL((pack_split<OffT, 256, 2>), dim3(grid), dim3(kThreads), 0, s, a);

@@ -290,6 +290,7 @@ static famlies_status analyze_impl(int dtype, int compute, const famlies_tensor*
     t.split = 1;
     t.tail = 0;
   }
+  if (split_parts(an.compute)) t.bk = split_slice_k(split_parts(an.compute));
   int kchunk = 0, head = 0;
   finalize_split(&t, an.K, ceil_div(an.M, t.bm) * ceil_div(an.N, t.bn), &kchunk, &head);
   int ib = 64;

@@ -8,9 +8,10 @@
 //   bf16x6 (NS = 3): h, m = RNE_bf16(x - h), l = RNE_bf16(x - h - m);
 //                    x*y ~= hh + (hm + mh) + (hl + mm + lh)   (6 products)
 // (every difference is exact in FP32).  Products of the same order go to one
-// FP32 MFMA accumulator; the epilogue adds the orders in FP64 together with
-// alpha, beta and C, and stores FP32 (new and mixed precisions: Introduction,
-// "Challenges"; "Supporting new and mixed precisions").
+// FP32 MFMA accumulator (in bf16x6 the orders 1 and 2 share one); the
+// epilogue adds the accumulators in FP64 together with alpha, beta and C,
+// and stores FP32 (new and mixed precisions: Introduction, "Challenges";
+// "Supporting new and mixed precisions").
 #include "device.hpp"
 #include "runtime.hpp"
 
@@ -39,9 +40,14 @@ __device__ __forceinline__ void split2(float x0, float x1, uint32_t* parts) {
   }
 }
 
-// bf16 LDS tiles: [row][k] with 16-byte aligned rows of BK + 8 entries.
-constexpr int kB3K = 32;            // contraction slice per stage
-constexpr int kB3LD = kB3K + 8;     // row pitch in bf16
+// bf16 LDS tiles: [row][k] with 16-byte aligned rows of BK + 8 entries,
+// BK the contraction slice per stage: 32 for bf16x3, 16 for bf16x6 (whose
+// three part planes per operand then leave room in the CU's 160 KB of LDS
+// for two workgroups).
+template <int NS>
+constexpr int kSplitBK = split_slice_k(NS);
+template <int NS>
+constexpr int kSplitLD = kSplitBK<NS> + 8;  // row pitch in bf16
 
 // Write the split of a gathered slice into the NS part tiles (part t at
 // tiles + t * tile_elems).  K-gathered threads own pairs of consecutive k's
@@ -55,7 +61,7 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
     for (int i = 0; i < G::E / 2; ++i) {
       uint32_t p[NS];
       split2<NS>(gg.template val<EDGE, S>(2 * i, k0, kend), gg.template val<EDGE, S>(2 * i + 1, k0, kend), p);
-      const int idx = gg.lds_index(2 * i, kB3LD);
+      const int idx = gg.lds_index(2 * i, kSplitLD<NS>);
 #pragma unroll
       for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
     }
@@ -66,7 +72,7 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
       uint32_t p0[NS], p1[NS];
       split2<NS>(gg.template val<EDGE, S>(4 * q, k0, kend), gg.template val<EDGE, S>(4 * q + 1, k0, kend), p0);
       split2<NS>(gg.template val<EDGE, S>(4 * q + 2, k0, kend), gg.template val<EDGE, S>(4 * q + 3, k0, kend), p1);
-      const int idx = gg.lds_index(4 * q, kB3LD);
+      const int idx = gg.lds_index(4 * q, kSplitLD<NS>);
 #pragma unroll
       for (int t = 0; t < NS; ++t) {
         const u32x2 w = {p0[t], p1[t]};
@@ -85,7 +91,7 @@ template <typename OffT, int BR, int NS, int MODE, int NSLOT = 1>
 struct SplitLoader {
   static_assert(MODE == kRowGather || MODE == kKGather, "every other mode has its own loader");
   static constexpr bool KF = MODE == kKGather;
-  using G = TileGather<float, OffT, BR, kB3K, KF, KF ? 2 : 1, NSLOT>;
+  using G = TileGather<float, OffT, BR, kSplitBK<NS>, KF, KF ? 2 : 1, NSLOT>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
@@ -95,7 +101,7 @@ struct SplitLoader {
   __device__ __forceinline__ void load(const void* base) { g.template load<S>(static_cast<const float*>(base)); }
   template <int S = 0>
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int k0, int kend) const {
-    if (k0 + kB3K <= kend)
+    if (k0 + kSplitBK<NS> <= kend)
       store_split<NS, G, KF, false, S>(g, tiles, tile_elems, k0, kend);
     else
       store_split<NS, G, KF, true, S>(g, tiles, tile_elems, k0, kend);
@@ -122,7 +128,7 @@ __device__ __forceinline__ void store_split4(float x0, float x1, float x2, float
 // (every slice whole: the planner takes this loader only when BK divides K).
 template <typename OffT, int BR, int NS, int NSLOT>
 struct SplitLoader<OffT, BR, NS, kVecK, NSLOT> {
-  using G = VecKGather<float, OffT, BR, kB3K, NSLOT>;
+  using G = VecKGather<float, OffT, BR, kSplitBK<NS>, NSLOT>;
   G g;
   int nkb = 0;
   __device__ __forceinline__ void init(const OffT* mnoff, int tile_r0, int tid) { g.init(mnoff, tile_r0, tid); }
@@ -135,7 +141,7 @@ struct SplitLoader<OffT, BR, NS, kVecK, NSLOT> {
 #pragma unroll
     for (int i = 0; i < G::NR; ++i) {
       const auto v = g.v[S][i];
-      store_split4<NS>(v[0], v[1], v[2], v[3], tiles, tile_elems, (g.r0 + i * G::RSTEP) * kB3LD + g.kk0);
+      store_split4<NS>(v[0], v[1], v[2], v[3], tiles, tile_elems, (g.r0 + i * G::RSTEP) * kSplitLD<NS> + g.kk0);
     }
   }
 };
@@ -143,8 +149,9 @@ struct SplitLoader<OffT, BR, NS, kVecK, NSLOT> {
 template <typename OffT, int BR, int NS, int NSLOT>
 struct SplitLoader<OffT, BR, NS, kPacked, NSLOT> {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-  static constexpr int VPT = BR * kB3K / 8 / kThreads;  // 16-byte vectors per thread and part
-  static_assert(VPT >= 1, "packed block does not divide the workgroup");
+  static constexpr int BK = kSplitBK<NS>;
+  static constexpr int NV = BR * BK / 8;                      // 16-byte vectors per part of a block
+  static constexpr int VPT = (NV + kThreads - 1) / kThreads;  // per thread (the last one partly idle)
   u32x4 v[NSLOT][NS][VPT];
   int tile = 0, kb[NSLOT] = {}, nkb = 1, tid = 0;
   __device__ __forceinline__ void init(const OffT*, int tile_r0, int t) {
@@ -152,14 +159,16 @@ struct SplitLoader<OffT, BR, NS, kPacked, NSLOT> {
     tid = t;
   }
   template <int S = 0>
-  __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb[S] = k0 / kB3K; }
+  __device__ __forceinline__ void fetch_k(const OffT*, int k0) { kb[S] = k0 / BK; }
   template <int S = 0>
   __device__ __forceinline__ void load(const void* base) {
-    const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb[S]) * (size_t)(NS * BR * kB3K);
+    const __bf16* blk = static_cast<const __bf16*>(base) + ((size_t)tile * nkb + kb[S]) * (size_t)(NS * BR * BK);
 #pragma unroll
     for (int t = 0; t < NS; ++t)
 #pragma unroll
-      for (int q = 0; q < VPT; ++q) v[S][t][q] = reinterpret_cast<const u32x4*>(blk + t * BR * kB3K)[tid + q * kThreads];
+      for (int q = 0; q < VPT; ++q)
+        if (NV % kThreads == 0 || tid + q * kThreads < NV)
+          v[S][t][q] = reinterpret_cast<const u32x4*>(blk + t * BR * BK)[tid + q * kThreads];
   }
   template <int S = 0>
   __device__ __forceinline__ void store(__bf16* tiles, int tile_elems, int, int) const {
@@ -167,8 +176,9 @@ struct SplitLoader<OffT, BR, NS, kPacked, NSLOT> {
     for (int t = 0; t < NS; ++t)
 #pragma unroll
       for (int q = 0; q < VPT; ++q) {
+        if (NV % kThreads != 0 && tid + q * kThreads >= NV) continue;
         const int e = (tid + q * kThreads) * 8;
-        *reinterpret_cast<u32x4*>(tiles + t * tile_elems + (e / kB3K) * kB3LD + e % kB3K) = v[S][t][q];
+        *reinterpret_cast<u32x4*>(tiles + t * tile_elems + (e / BK) * kSplitLD<NS> + e % BK) = v[S][t][q];
       }
   }
 };
@@ -190,14 +200,20 @@ constexpr int kSplitDepth = BM == 256 ? 1 : 2;
 // blocks and B row-gathered: 201 -> 261 TFLOP/s).  Both operands row-gathered
 // or both element-gathered along K, 64-bit offsets with a row-gathered
 // operand (74 to 111 registers spilled) and the other tiles stay at one.
+// The 128 x 128 bf16x6 tile runs two workgroups per CU under the same
+// operand conditions with 32-bit offsets: its 16-deep slices take 74 KB of
+// LDS for both stages, and its two accumulator sets leave the registers for
+// two slices in flight (ring 10.80 -> 9.02 ms, ladder v=128 o=32 3.31 ->
+// 2.94 ms, ladder v=192 o=48 40.0 -> 35.6 ms against 32-deep slices at one
+// workgroup per CU; bf16x3 with 16-deep slices was 4 to 9 % slower).
 template <typename OffT, int BM, int NS, int XM, int YM>
 constexpr int kSplitWgPerCu =
-    (BM == 128 && NS == 2 && !(XM == kKGather && YM == kKGather) && !(XM == kRowGather && YM == kRowGather) &&
-     ((XM != kRowGather && YM != kRowGather) || sizeof(OffT) == 4)) ? 2 : 1;
+    (BM == 128 && !(XM == kKGather && YM == kKGather) && !(XM == kRowGather && YM == kRowGather) &&
+     (NS == 2 ? ((XM != kRowGather && YM != kRowGather) || sizeof(OffT) == 4) : sizeof(OffT) == 4)) ? 2 : 1;
 
 template <typename OffT, int BM, int BN, int XM, int YM, int NS>
 __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) void split_contract(PlainArgs<OffT> a) {
-  constexpr int BK = kB3K;
+  constexpr int BK = kSplitBK<NS>, LD = kSplitLD<NS>;
   // Slices in flight: one workgroup per CU holds the accumulators, so the
   // next slice's loads must hide behind a single slice of bf16 MFMAs; two
   // slices in flight where the registers allow it.
@@ -206,7 +222,7 @@ __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) vo
   using GY = SplitLoader<OffT, BN, NS, YM, DEPTH>;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
-  constexpr int XS = BM * kB3LD, YS = BN * kB3LD;  // bf16 elements per part tile
+  constexpr int XS = BM * LD, YS = BN * LD;  // bf16 elements per part tile
   constexpr int STAGE = NS * (XS + YS);            // all parts of both tiles
   __shared__ __attribute__((aligned(16))) __bf16 smem[2 * STAGE];
 
@@ -240,9 +256,14 @@ __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) vo
   gx.nkb = a.x_nkb;
   gy.nkb = a.y_nkb;
 
-  f32x16 acc[NS][MB][NB];  // acc[o]: products whose parts' orders sum to o
+  // acc[o]: products whose parts' orders sum to o; in bf16x6 the orders 1
+  // and 2 (five products, each below 2^-8 |x||y|) share acc[1], so that two
+  // workgroups fit per CU
+  constexpr int NA = NS == 3 ? 2 : NS;
+  auto slot_of = [](int o) { return o < NA ? o : NA - 1; };
+  f32x16 acc[NA][MB][NB];
 #pragma unroll
-  for (int o = 0; o < NS; ++o)
+  for (int o = 0; o < NA; ++o)
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -258,18 +279,18 @@ __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) vo
   auto multiply = [&](int cur) {
     const __bf16* xs = smem + cur * STAGE;
     const __bf16* ys = xs + NS * XS;
-    // lane group g covers k in [16g, 16g + 16) of the slice, in two steps of 8
+    // lane group g covers k in [g BK/2, (g + 1) BK/2) of the slice, in steps of 8
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < BK / 16; ++s) {
       bf16x8 av[NS][MB], bv[NS][NB];
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
 #pragma unroll
         for (int i = 0; i < MB; ++i)
-          av[p][i] = *reinterpret_cast<const bf16x8*>(xs + p * XS + (wm * WTM + i * 32 + r) * kB3LD + g * 16 + s * 8);
+          av[p][i] = *reinterpret_cast<const bf16x8*>(xs + p * XS + (wm * WTM + i * 32 + r) * LD + g * (BK / 2) + s * 8);
 #pragma unroll
         for (int j = 0; j < NB; ++j)
-          bv[p][j] = *reinterpret_cast<const bf16x8*>(ys + p * YS + (wn * WTN + j * 32 + r) * kB3LD + g * 16 + s * 8);
+          bv[p][j] = *reinterpret_cast<const bf16x8*>(ys + p * YS + (wn * WTN + j * 32 + r) * LD + g * (BK / 2) + s * 8);
       }
 #pragma unroll
       for (int i = 0; i < MB; ++i)
@@ -279,7 +300,7 @@ __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) vo
           for (int pa = 0; pa < NS; ++pa)
 #pragma unroll
             for (int pb = 0; pa + pb < NS; ++pb)
-              acc[pa + pb][i][j] = mma_bf16(av[pa][i], bv[pb][j], acc[pa + pb][i][j]);
+              acc[slot_of(pa + pb)][i][j] = mma_bf16(av[pa][i], bv[pb][j], acc[slot_of(pa + pb)][i][j]);
     }
   };
   constexpr auto slot0 = std::integral_constant<int, 0>{};
@@ -349,7 +370,7 @@ __global__ __launch_bounds__(kThreads, (kSplitWgPerCu<OffT, BM, NS, XM, YM>)) vo
   auto total = [&](int i, int j, int e) {
     double v = 0.0;
 #pragma unroll
-    for (int o = NS - 1; o >= 0; --o) v += (double)acc[o][i][j][e];  // smallest order first
+    for (int o = NA - 1; o >= 0; --o) v += (double)acc[o][i][j][e];  // smallest order first
     return v;
   };
   if (a.splits == 1) {
