@@ -209,7 +209,7 @@ static famlies_status prepare_plan(famlies_handle_s* h, famlies_plan_s* p, int d
     if (!split_tile_supported(ns, p->cfg.bm, p->cfg.bn)) p->cfg.bm = p->cfg.bn = 128;
   } else if (!plain_tile_supported(dtype, p->cfg.bm, p->cfg.bn, p->cfg.bk)) {
     p->cfg.bm = p->cfg.bn = 128;
-    p->cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
+    p->cfg.bk = dtype == FAMLIES_F64 ? 8 : 32;
   }
   if (an.L > 1) p->cfg.split = 1;  // batch modes already multiply the tile count
   const int64_t ntiles = ceil_div(an.M, p->cfg.bm) * ceil_div(an.N, p->cfg.bn);

@@ -73,10 +73,10 @@ static hipError_t launch_pack_t(const PackArgs<OffT>& a, int dtype, int ns, int 
   const int64_t total = (int64_t)a.L * a.tiles * a.nkb * br * bk;
   const int grid = (int)std::min<int64_t>((total + kThreads - 1) / kThreads, 8192);
   if (ns == 0) {
-    if (dtype == FAMLIES_F64 && br == 128 && bk == 16)
-      hipLaunchKernelGGL((pack_plain<double, OffT, 128, 16>), dim3(grid), dim3(kThreads), 0, s, a);
-    else if (dtype == FAMLIES_F64 && br == 64 && bk == 16)
-      hipLaunchKernelGGL((pack_plain<double, OffT, 64, 16>), dim3(grid), dim3(kThreads), 0, s, a);
+    if (dtype == FAMLIES_F64 && br == 128 && bk == 8)
+      hipLaunchKernelGGL((pack_plain<double, OffT, 128, 8>), dim3(grid), dim3(kThreads), 0, s, a);
+    else if (dtype == FAMLIES_F64 && br == 64 && bk == 8)
+      hipLaunchKernelGGL((pack_plain<double, OffT, 64, 8>), dim3(grid), dim3(kThreads), 0, s, a);
     else if (dtype == FAMLIES_F32 && br == 128 && bk == 32)
       hipLaunchKernelGGL((pack_plain<float, OffT, 128, 32>), dim3(grid), dim3(kThreads), 0, s, a);
     else if (dtype == FAMLIES_F32 && br == 64 && bk == 32)

@@ -22,16 +22,19 @@ namespace famlies {
 
 template <typename T, typename OffT, int BM, int BN, int BK, int XM, int YM>
 __global__ __launch_bounds__(kThreads, FAMLIES_PLAIN_WAVES_PER_EU) void plain_contract(PlainArgs<OffT> a) {
-  // Two slices in flight where the registers allow it: FP32 tiles with a
+  // Two slices in flight where the registers allow it: tiles with a
   // row-gathered operand and 32-bit offsets (one load per element along K,
   // so its slice takes longest to arrive), and tiles whose operands are both
   // read in affine 16-byte blocks (few registers per slice; FP64 only with
   // 32-bit offsets).  Measured on the ladder (both affine): FP64 82 -> 87 %,
-  // FP32 83 -> 88 %, FP32 with 64-bit offsets 77 -> 85 % of peak.  Other
-  // FP64 tiles would spill (the accumulators take half the registers); with
-  // both operands element-gathered along K the deeper pipeline was no faster.
+  // FP32 83 -> 88 %, FP32 with 64-bit offsets 77 -> 85 % of peak.  FP64
+  // slices are 8 deep (the FP64 MFMA takes 4 k's, so two steps per slice):
+  // half the staging registers of 16-deep slices, which lets the FP64 tile
+  // with a row-gathered operand keep two slices in flight too (ring o=48
+  // v=192 83.1 -> 85.5 %; ladder 87.0 -> 87.7 %).  With both operands
+  // element-gathered along K the deeper pipeline was no faster.
   static constexpr int kDepth =
-      ((sizeof(OffT) == 4 && sizeof(T) == 4 && (XM == kRowGather || YM == kRowGather)) ||
+      ((sizeof(OffT) == 4 && (XM == kRowGather || YM == kRowGather)) ||
        ((sizeof(OffT) == 4 || sizeof(T) == 4) && XM == kVecK && YM == kVecK))
           ? 2
           : 1;
@@ -173,7 +176,7 @@ static hipError_t launch_plain_t(const PlainArgs<OffT>& a, const PlainLaunch& L,
   }
   const int64_t ntiles = (int64_t)a.tiles_m * a.tiles_n;
   const int grid = (int)(a.splits == 1 ? ntiles * a.L : a.head + (ntiles - a.head) * a.splits);
-  constexpr int BK = sizeof(T) == 8 ? 16 : 32;
+  constexpr int BK = sizeof(T) == 8 ? 8 : 32;
   hipError_t e = hipErrorInvalidValue;
   if (L.bm == 128 && L.bn == 128 && L.bk == BK)
     e = launch_tile<T, OffT, 128, 128, BK>(a, L.xm, L.ym, grid, s);
@@ -202,7 +205,7 @@ hipError_t launch_plain(int dtype, const PlainArgs<int64_t>& a, const PlainLaunc
 }
 
 bool plain_tile_supported(int dtype, int bm, int bn, int bk) {
-  const int BK = dtype == FAMLIES_F64 ? 16 : 32;
+  const int BK = dtype == FAMLIES_F64 ? 8 : 32;
   return bk == BK && ((bm == 128 && bn == 128) || (bm == 64 && bn == 64));
 }
 

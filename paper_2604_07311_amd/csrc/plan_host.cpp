@@ -43,7 +43,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // only ranks candidates; it is not a timing.
 TileCfg choose_tiles(const famlies_handle_s* h, const Analysis& an, bool* from_table) {
   TileCfg t;
-  const int bk = an.dtype == FAMLIES_F64 ? 16 : 32;
+  const int bk = an.dtype == FAMLIES_F64 ? 8 : 32;
   t.bk = bk;
   if (from_table) *from_table = false;
   if (an.M == 0 || an.N == 0 || an.K == 0) return t;

@@ -327,7 +327,7 @@ int analyze(int dtype, int compute, const famlies_tensor* A, const famlies_tenso
       std::vector<Mode> q{an.P[iu], an.P[iw]};
       for (size_t r = 0; r < an.P.size(); ++r)
         if (r != iu && r != iw) q.push_back(an.P[r]);
-      const int64_t bk = an.esize == 8 ? 16 : 32;
+      const int64_t bk = an.esize == 8 ? 8 : 32;  // the plain kernels' K slice
       q[0].blk = std::min<int64_t>(q[0].ext, bk == 32 ? 8 : 4);
       q[1].blk = std::max<int64_t>(1, std::min<int64_t>(q[1].ext, bk / q[0].blk));
       an.P = q;

@@ -114,7 +114,7 @@ famlies_status tune_plain(famlies_handle_s* h, const Buffers& buf, int64_t cap, 
           for (int bt : {64, 128}) {
             TileCfg t;
             t.bm = t.bn = bt;
-            t.bk = md.dtype == FAMLIES_F64 ? 16 : 32;
+            t.bk = md.dtype == FAMLIES_F64 ? 8 : 32;
             t.split = 1;
             cands.push_back(t);
             const int64_t tiles = ((M + bt - 1) / bt) * ((N + bt - 1) / bt);

@@ -200,7 +200,7 @@ def _mk(labels, ext, orders, pads=(None, None, None)):
 
 def test_affine_block_flags(fm):
     """Block strides: the plan reads an operand with 16-byte loads (kernel id
-    +16 for X, +32 for Y) exactly when it is K-gathered, the K slice (16 FP64
+    +16 for X, +32 for Y) exactly when it is K-gathered, the K slice (8 FP64
     / 32 FP32 elements) divides K, each K-slice of its indexing vector steps
     by one element, and every run start is a multiple of the 16-byte vector
     (2 FP64 or 4 FP32 elements)."""
@@ -218,12 +218,14 @@ def test_affine_block_flags(fm):
     rows30 = _mk(("ki", "kj", "ji"), {"k": 30, "i": 20, "j": 6}, (None, None, None))
     assert analyze(fm, rows30, F64)[0]["kernel"] == 1
     assert analyze(fm, rows30, F32)[0]["kernel"] == 1
-    # K modes that do not fuse and a K extent that splits the 32-wide slices
-    split = _mk(("kil", "klj", "ij"), {"k": 40, "l": 3, "i": 20, "j": 8}, ([0, 1, 2], [0, 2, 1], [0, 1]))
-    info, _ = analyze(fm, split, F32)
+    # K modes that do not fuse and a K extent that splits the slices
+    split = _mk(("kil", "klj", "ij"), {"k": 36, "l": 3, "i": 20, "j": 8}, ([0, 1, 2], [0, 2, 1], [0, 1]))
+    info, _ = analyze(fm, split, F32)                       # 32-wide slices: 36 = 32+4
     assert info["kernel"] & 48 == 0
-    info, _ = analyze(fm, split, F64)                       # 16-wide slices: 40 = 16+16+8 still splits
+    info, _ = analyze(fm, split, F64)                       # 8-wide slices: 36 = 4*8+4 still splits
     assert info["kernel"] & 48 == 0
+    k40 = _mk(("kil", "klj", "ij"), {"k": 40, "l": 3, "i": 20, "j": 8}, ([0, 1, 2], [0, 2, 1], [0, 1]))
+    assert analyze(fm, k40, F64)[0]["kernel"] & 48 == 48    # 40 = 5*8: every 8-wide slice inside one run
     # a row-gathered operand never takes the flag; the split precisions do
     ring = synth.ring(4, 8, seed=1)
     info, _ = analyze(fm, ring, F32)
@@ -234,9 +236,9 @@ def test_affine_block_flags(fm):
 
 def test_blocked_k_enumeration(fm):
     """A is fastest along p, B along q, both contracted: K is enumerated in
-    8 x 4 (FP32) or 4 x 4 (FP64) blocks of (p, q), so every 32-wide K slice
-    holds runs of consecutive elements of both operands; the kernel view still
-    reproduces the oracle exactly."""
+    8 x 4 (FP32) or 4 x 2 (FP64) blocks of (p, q), so every K slice (32 deep,
+    8 deep) holds runs of consecutive elements of both operands; the kernel
+    view still reproduces the oracle exactly."""
     import oracle
     ext = {"i": 20, "p": 12, "q": 10, "j": 18}
     a = synth.layout([ext["i"], ext["p"], ext["q"]], order=[1, 0, 2])   # A[i,p,q]: p fastest
@@ -245,7 +247,7 @@ def test_blocked_k_enumeration(fm):
     p = synth.Problem("blocked", "ipq", "qpj", "ji", a, b, c, 1.0, 0.5)
     rng = np.random.default_rng(9)
     p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "int") for t in (p.a, p.b, p.c))
-    for dt, (bu, bw) in ((fm.FAMLIES_F32, (8, 4)), (fm.FAMLIES_F64, (4, 4))):
+    for dt, (bu, bw) in ((fm.FAMLIES_F32, (8, 4)), (fm.FAMLIES_F64, (4, 2))):
         info, off = analyze(fm, p, dt, offsets=True)
         assert info["x_kfast"] == 1 and info["y_kfast"] == 1
         X, Y = (p.b, p.a) if info["swapped"] else (p.a, p.b)
@@ -383,7 +385,7 @@ def test_plan_log(tmp_path):
     assert r.returncode == 0, r.stderr
     lines = [l for l in r.stderr.splitlines() if l.startswith("[famlies]")]
     assert len(lines) == 1, r.stderr
-    assert "analyze f64/native M=1024 N=16384 K=16384" in lines[0] and "tile=128x128x16" in lines[0], lines[0]
+    assert "analyze f64/native M=1024 N=16384 K=16384" in lines[0] and "tile=128x128x8" in lines[0], lines[0]
     env["FAMLIES_LOG"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
     assert "[famlies]" not in r.stderr

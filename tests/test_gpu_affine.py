@@ -50,7 +50,7 @@ def _forced_plan(gpu, tmp_path, p, dtype, bm):
     lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
     path = tmp_path / ("tiles_%s_%d.txt" % (dtype, bm))
     path.write_text("plain %d 0 %d %d %d %d %d %d 1\n" % (code, lg(info["m"]), lg(info["n"]), lg(info["k"]), bm, bm,
-                                                          16 if dtype == "f64" else 32))
+                                                          8 if dtype == "f64" else 32))
     h = fm.famlies_create(0)
     fm.famlies_load_tune_table(h, str(path))
     plan = fm.famlies_plan_contract(h, code, 0, *descs)
@@ -83,13 +83,14 @@ def _check(gpu, p, dtype, K, expect_kernel_bits, tmp_path=None, bm=None):
 @pytest.mark.parametrize("bm", [None, 128])
 def test_fused_k_ragged(gpu, tmp_path, dtype, bm):
     """A[k,l,i] B[k,l,j] -> C[j,i]: K = 40*16 = 640 fuses to one unit-stride
-    mode, a multiple of the K slice; then K = 40*13 = 520, which is not, and
-    both operands are gathered (planned tiles, then forced 128 x 128)."""
+    mode, a multiple of the K slice; then K = 36*13 = 468, a multiple of
+    neither slice (8 FP64, 32 FP32 elements), and both operands are gathered
+    (planned tiles, then forced 128 x 128)."""
     ext = {"k": 40, "l": 16, "i": 600, "j": 520}
     p = _problem("kli", "klj", "ji", ext, (None, None, None), seed=201)
     got = _check(gpu, p, dtype, 640, 48, tmp_path, bm)
-    ext13 = dict(ext, l=13)
-    _check(gpu, _problem("kli", "klj", "ji", ext13, (None, None, None), seed=205), dtype, 520, 0, tmp_path, bm)
+    ext13 = dict(ext, k=36, l=13)
+    _check(gpu, _problem("kli", "klj", "ji", ext13, (None, None, None), seed=205), dtype, 468, 0, tmp_path, bm)
     # unaligned base pointers: same plan shape, gathering path, same values up to rounding
     q = _shift(p)
     got_q = _check(gpu, q, dtype, 640, 48, tmp_path, bm)

@@ -38,7 +38,7 @@ def _plan64(gpu, tmp_path, p, dtype, compute="native", bm=None, form="64"):
     info, _ = fm.famlies_analyze(code, comp, *descs)
     lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
     b = bm or info["tile_m"]
-    bk = 16 if (dtype == "f64" and compute == "native") else 32
+    bk = 8 if (dtype == "f64" and compute == "native") else 32
     path = tmp_path / ("t%s_%s_%s.txt" % (form, dtype, compute))
     path.write_text("plain %d %d %d %d %d %d %d %d %d %s\n" % (code, comp, lg(info["m"]), lg(info["n"]),
                                                               lg(info["k"]), b, b, bk, info["split_k"], form))
@@ -64,11 +64,12 @@ def _run64(gpu, tmp_path, p, dtype, compute="native", bm=None, form="64"):
 @pytest.mark.parametrize("bm", [64, 128])
 @pytest.mark.parametrize("v", [24, 32])
 def test_ladder_64bit(gpu, tmp_path, dtype, bm, v, form):
-    """v = 24: only T's fused K is read in affine blocks (W's e-runs of 24
-    split the K slices); v = 32: both operands are."""
+    """v = 24: in FP32 only T's fused K is read in affine blocks (W's e-runs
+    of 24 split the 32-wide K slices), in FP64 both are (8-wide slices);
+    v = 32: both operands are."""
     p = round_inputs(synth.ladder(v, 8, seed=301), dtype)
     got, info = _run64(gpu, tmp_path, p, dtype, bm=bm, form=form)
-    assert info["kernel"] & 48 == (48 if v == 32 else 16)
+    assert info["kernel"] & 48 == (48 if v == 32 or dtype == "f64" else 16)
     want, d = oracle.contract(p.alpha, *p.oracle_args()[:4], p.beta, *p.oracle_args()[4:], want_cond=True)
     (check_fp64 if dtype == "f64" else check_fp32)(got, want, d, v * v)
 

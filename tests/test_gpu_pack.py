@@ -31,7 +31,7 @@ def _forced_handle(fm, tmp_path, p, dtype, compute, bm, split=1):
                                  fm.make_desc(p.b.extents, p.b.strides, p.lb),
                                  fm.make_desc(p.c.extents, p.c.strides, p.lc))
     lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
-    bk = 16 if dtype == "f64" else 32
+    bk = 8 if dtype == "f64" else 32
     path = tmp_path / ("tiles_%s_%s.txt" % (dtype, compute))
     path.write_text("plain %d %d %d %d %d %d 128 %d %d\n" % (
         code, comp, lg(info["m"]), lg(info["n"]), lg(info["k"]), bm, bk, split))

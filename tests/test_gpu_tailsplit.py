@@ -41,7 +41,7 @@ def test_tail_split_matches_oracle(gpu, tmp_path, dtype, bm, split, tail, which)
         pytest.skip("one tile: nothing to split off")
     tail = ntiles - 1 if tail < 0 else min(tail, ntiles - 1)
     code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-    bk = 16 if dtype == "f64" else 32
+    bk = 8 if dtype == "f64" else 32
     descs = [fm.make_desc(t.extents, t.strides, lab) for t, lab in ((p.a, p.la), (p.b, p.lb), (p.c, p.lc))]
     info, _ = fm.famlies_analyze(code, 0, *descs)
     lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
@@ -121,7 +121,7 @@ def test_tail_split_affine_short_units(gpu, tmp_path, dtype, split, tail):
     p.abuf, p.bbuf, p.cbuf = (synth.fill(rng, t, "uniform") for t in (p.a, p.b, p.c))
     p = round_inputs(p, dtype)
     code = fm.FAMLIES_F64 if dtype == "f64" else fm.FAMLIES_F32
-    bk = 16 if dtype == "f64" else 32
+    bk = 8 if dtype == "f64" else 32
     descs = [fm.make_desc(t.extents, t.strides, lab) for t, lab in ((p.a, p.la), (p.b, p.lb), (p.c, p.lc))]
     info, _ = fm.famlies_analyze(code, 0, *descs)
     lg = lambda x: int(np.ceil(np.log2(max(x, 1))))
