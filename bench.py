@@ -263,15 +263,15 @@ def cpu_baseline(p, target_s=12.0):
 # plan's launch shape (`plan` = plan_signature() then).  After a change to
 # either the traffic is reported as null until the counters are taken again.
 TRAFFIC = {
-    # plain_contract<double,u32,128,128,16,3,3>, ladder v=128 o=32
-    ("ladder", "f64", 128, 32): {"fetch_kib": 3.55754e6, "write_kib": 131072.0, "fetch_scale": 1.99990,
-                                 "write_scale": 1.0, "sources": "8581e291bf2d496d",
-                                 "plan": "128x128x16 split1/0 kernel49 bits32",
+    # plain_contract<double,u32,128,128,8,3,3>, ladder v=128 o=32
+    ("ladder", "f64", 128, 32): {"fetch_kib": 3.06707e6, "write_kib": 131072.0, "fetch_scale": 1.99989,
+                                 "write_scale": 1.0, "sources": "89c222de133bcc5c",
+                                 "plan": "128x128x8 split1/0 kernel49 bits32",
                                  "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, "
                                             "profiles/plain_contract_ladder_v128_o32_write_size.md"},
     # plain_contract<float,u32,128,128,32,3,3>, ladder v=128 o=32
-    ("ladder", "f32", 128, 32): {"fetch_kib": 2.97599e6, "write_kib": 65536.0, "fetch_scale": 1.99990,
-                                 "write_scale": 1.0, "sources": "8581e291bf2d496d",
+    ("ladder", "f32", 128, 32): {"fetch_kib": 2.81782e6, "write_kib": 65536.0, "fetch_scale": 1.99989,
+                                 "write_scale": 1.0, "sources": "89c222de133bcc5c",
                                  "plan": "128x128x32 split1/0 kernel49 bits32",
                                  "profile": "profiles/plain_contract_ladder_v128_o32_fetch_size.md, "
                                             "profiles/plain_contract_ladder_v128_o32_write_size.md"},
