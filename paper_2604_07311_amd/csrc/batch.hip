@@ -67,19 +67,18 @@ constexpr int kBatchClasses = 4;
 __host__ __device__ constexpr int batch_class_bm(int cls) { return (cls & 1) ? 128 : 64; }
 __host__ __device__ constexpr int batch_class_bn(int cls) { return (cls & 2) ? 128 : 64; }
 
-// K slice and slices in flight of the batched item body.  The items are
-// short in K (tens of slices) and their operands mostly miss L2, so the
-// loads' lead time decides: FP32 takes 16-deep slices with two in flight
-// (the lead of one 32-deep slice, in finer steps).  On the 20,000-problem
-// workload, against 32-deep slices with one in flight: 174.6 -> 166.7 ms;
-// 16-deep with one in flight (half the lead) 184.8 ms.  FP64 keeps one
-// 16-deep slice in flight.
-__host__ __device__ constexpr int batch_slice_k(int esize) { return 16; }
+// Slices in flight of the batched item body (its K slice is
+// batch_slice_k()).  The items are short in K (tens of slices) and their
+// operands mostly miss L2, so the loads' lead time decides: FP32 takes
+// 16-deep slices with two in flight (the lead of one 32-deep slice, in finer
+// steps).  On the 20,000-problem workload, against 32-deep slices with one
+// in flight: 174.6 -> 166.7 ms; 16-deep with one in flight (half the lead)
+// 184.8 ms.  FP64 keeps one 16-deep slice in flight.
 __host__ __device__ constexpr int batch_depth(int esize) { return esize == 4 ? 2 : 1; }
 
 template <typename T, int BM, int BN, bool XK, bool YK>
 __device__ __forceinline__ void run_item(const TileJob<uint32_t>& j, T* smem) {
-  constexpr int BK = batch_slice_k(sizeof(T));
+  constexpr int BK = batch_slice_k();
   constexpr int kDepth = batch_depth(sizeof(T));
   PlainTile<T, BM, BN, BK, XK ? kKGather : kRowGather, YK ? kKGather : kRowGather, kDepth>::template run<uint32_t>(
       j, smem);
@@ -110,7 +109,7 @@ __device__ __forceinline__ P* uniform(P* p) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads, 2) void batch_contract(BatchArgs a) {
-  constexpr int BK = batch_slice_k(sizeof(T));
+  constexpr int BK = batch_slice_k();
   constexpr int SM = PlainTile<T, 128, 128, BK, true, true>::SMEM;
   __shared__ T smem[SM];
   __shared__ int next;
@@ -249,7 +248,7 @@ famlies_status batch_plan_make(famlies_handle_s* h, famlies_plan_s** out, int dt
   std::vector<std::vector<Job>> per_prob((size_t)n);
   std::vector<double> prob_cost((size_t)n, 0.0);
   int64_t table_hits = 0;
-  const int BK = batch_slice_k(dtype == FAMLIES_F64 ? 8 : 4);
+  const int BK = batch_slice_k();
   for (int64_t p = 0; p < n; ++p) {
     Analysis an;
     std::string err;

@@ -185,6 +185,8 @@ inline int split_parts(int compute) { return compute == FAMLIES_BF16X6 ? 3 : com
 // Contraction slice (BK) of the split-bf16 kernels with ns parts per operand:
 // 32 for bf16x3, 16 for bf16x6 (three part planes per operand in LDS).
 constexpr int split_slice_k(int ns) { return ns == 3 ? 16 : 32; }
+// Contraction slice of the batched kernel's items (both element types).
+constexpr int batch_slice_k() { return 16; }
 // FP64 on INT8 MFMA: the number of digit slices, 0 for other compute modes.
 inline int int8_slices(int compute) {
   return compute >= FAMLIES_INT8X3 && compute <= FAMLIES_INT8X7 ? compute - FAMLIES_INT8X3 + 3 : 0;

@@ -237,7 +237,7 @@ famlies_status tune_batch(famlies_handle_s* h, const Buffers& buf, int64_t cap, 
           en.lk = lk;
           en.cfg.bm = (bcls & 1) ? 128 : 64;
           en.cfg.bn = (bcls & 2) ? 128 : 64;
-          en.cfg.bk = dtype == FAMLIES_F64 ? 16 : 32;
+          en.cfg.bk = batch_slice_k();
           en.cfg.split = 1;
           fresh->put(en);
         }

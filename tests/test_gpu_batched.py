@@ -175,7 +175,7 @@ def test_batched_graph_replay():
 def _class_table(path, dtype_code, bm, bn):
     """A tile table whose batch entries give every size class the tile
     bm x bn."""
-    bk = 16 if dtype_code == 1 else 32
+    bk = 16  # the batched kernel's K slice (recorded, not used to pick the class)
     with open(path, "w") as f:
         f.write("# every batched size class: %d x %d\n" % (bm, bn))
         for lm in range(14):
