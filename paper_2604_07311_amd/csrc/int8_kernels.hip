@@ -272,6 +272,11 @@ __device__ __forceinline__ int acc_row(int l, int r) { return 8 * (r / 4) + 4 * 
 // operand reads of 16 consecutive rows cover all 64 banks once).
 constexpr int kI8Step = 32;
 constexpr int kI8StepPitch = 48;
+// Steps whose global loads are in flight while one is multiplied: two up to
+// six digit slices (the second register set fits beside the S accumulator
+// sets), one at seven.  The loads are plane chunks that mostly miss L2; with
+// one step of lead (about 0.5 us of MFMA work) the GEMM waited on them.
+constexpr int int8_gemm_lead(int S) { return S <= 6 ? 2 : 1; }
 
 template <typename OffT, int S>
 __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
@@ -291,27 +296,46 @@ __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
   // A step is 32 contracted indices, half of a 64-k block of the planes:
   // per plane X 128 rows x 32 bytes (one 16-byte chunk per thread), Y 64 rows
   // x 32 bytes (threads < 128).  Chunk c: row c / 2, bytes 16 (c % 2).
-  const int crow = tid / 2, cofs = 16 * (tid % 2);
-  const bool ythr = tid < 2 * kI8BN;
-  i32x4 rx[S], ry[S];
-  auto fetch = [&](int st) {
+  // One step of one plane: X 128 rows x 32 bytes, one 16-byte chunk per
+  // thread; Y 64 rows x 32 bytes, with two register sets one 8-byte chunk
+  // per thread (half the registers), with one a 16-byte chunk per thread of
+  // the first 128.  Each group of 8 lanes stores 8 consecutive rows at one
+  // chunk offset (16-byte chunks), or 8 rows at two neighbouring offsets
+  // (8-byte chunks): at the 48-byte pitch their LDS banks are disjoint.
+  constexpr int NL = int8_gemm_lead(S);
+  constexpr bool kYHalf = NL == 2;
+  typedef int i32x2 __attribute__((ext_vector_type(2)));
+  typedef typename std::conditional<kYHalf, i32x2, i32x4>::type ychunk_t;
+  const int crow = ((tid >> 4) << 3) | (tid & 7), cofs = 16 * ((tid >> 3) & 1);
+  const int yrow = kYHalf ? ((tid >> 5) << 3) | ((tid >> 1) & 7) : crow;
+  const int yofs = kYHalf ? 8 * (2 * ((tid >> 4) & 1) + (tid & 1)) : cofs;
+  const bool ythr = kYHalf || tid < 2 * kI8BN;
+  const int st0 = 2 * g.kb0, st1 = 2 * g.kb1;
+  i32x4 rx[NL][S];
+  ychunk_t ry[NL][S];
+  // loads of step st into register set Q (steps past the last re-read it;
+  // their data is never stored)
+  auto fetch = [&](auto qc, int st) {
+    constexpr int Q = decltype(qc)::value;
+    st = st < st1 ? st : st1 - 1;
     const int64_t blk = (int64_t)(st / 2), half = 32 * (st % 2);
 #pragma unroll
     for (int t2 = 0; t2 < S; ++t2) {
-      rx[t2] = *global(reinterpret_cast<const i32x4*>(xb + t2 * xplane + blk * (kI8BM * kI8K) + crow * kI8K +
-                                                      half + cofs));
+      rx[Q][t2] = *global(reinterpret_cast<const i32x4*>(xb + t2 * xplane + blk * (kI8BM * kI8K) + crow * kI8K +
+                                                         half + cofs));
       if (ythr)
-        ry[t2] = *global(reinterpret_cast<const i32x4*>(yb + t2 * yplane + blk * (kI8BN * kI8K) + crow * kI8K +
-                                                        half + cofs));
+        ry[Q][t2] = *global(reinterpret_cast<const ychunk_t*>(yb + t2 * yplane + blk * (kI8BN * kI8K) +
+                                                              yrow * kI8K + half + yofs));
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](auto qc, int buf) {
+    constexpr int Q = decltype(qc)::value;
     unsigned char* bx = smem + buf * (XB + YB);
     unsigned char* by = bx + XB;
 #pragma unroll
     for (int t2 = 0; t2 < S; ++t2) {
-      *reinterpret_cast<i32x4*>(&bx[(t2 * kI8BM + crow) * kI8StepPitch + cofs]) = rx[t2];
-      if (ythr) *reinterpret_cast<i32x4*>(&by[(t2 * kI8BN + crow) * kI8StepPitch + cofs]) = ry[t2];
+      *reinterpret_cast<i32x4*>(&bx[(t2 * kI8BM + crow) * kI8StepPitch + cofs]) = rx[Q][t2];
+      if (ythr) *reinterpret_cast<ychunk_t*>(&by[(t2 * kI8BN + yrow) * kI8StepPitch + yofs]) = ry[Q][t2];
     }
   };
   i32x16 acc[S][2];
@@ -348,18 +372,13 @@ __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
         *cp = out;
       }
   };
-  // Steps [st0, st1) through two LDS buffers: the next step's loads are in
-  // flight while this one is multiplied, stored into the other buffer after,
-  // one barrier per step.
-  const int st0 = 2 * g.kb0, st1 = 2 * g.kb1;
-  fetch(st0);
-  stash(0);
-  __syncthreads();
-  for (int st = st0; st < st1; ++st) {
-    const int cur = (st - st0) & 1;
-    const bool more = st + 1 < st1;
-    if (more) fetch(st + 1);
-    const unsigned char* bx = smem + cur * (XB + YB);
+  // Steps [st0, st1) through two LDS buffers and NL register sets: step st
+  // is in set st % NL and buffer (st - st0) % 2.  A step first loads step
+  // st + NL into its own set (stored into LDS by the step before), then
+  // multiplies, then stores step st + 1 into the other buffer (its loads were
+  // issued NL - 1 steps earlier): one barrier per step.
+  auto multiply = [&](int buf) {
+    const unsigned char* bx = smem + buf * (XB + YB);
     const unsigned char* by = bx + XB;
     i32x4 yf[S];
 #pragma unroll
@@ -376,8 +395,29 @@ __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
         acc[t2 + u][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(x1, yf[u], acc[t2 + u][1], 0, 0, 0);
       }
     }
-    if (more) stash(cur ^ 1);
+  };
+  constexpr auto set0 = std::integral_constant<int, 0>{};
+  fetch(set0, st0);
+  if constexpr (NL == 2) fetch(std::integral_constant<int, 1>{}, st0 + 1);
+  stash(set0, 0);
+  __syncthreads();
+  auto step = [&](auto qc, int st) {
+    constexpr int Q = decltype(qc)::value;
+    const int cur = (st - st0) & 1;
+    const bool more = st + 1 < st1;
+    if constexpr (NL == 1) {
+      if (more) fetch(set0, st + 1);
+    } else {
+      fetch(qc, st + NL);
+    }
+    multiply(cur);
+    if (more) stash(std::integral_constant<int, (Q + 1) % NL>{}, cur ^ 1);
     __syncthreads();
+  };
+  for (int st = st0; st < st1; st += NL) {
+    step(set0, st);
+    if constexpr (NL == 2)
+      if (st + 1 < st1) step(std::integral_constant<int, 1>{}, st + 1);
   }
   update_c();
 }
