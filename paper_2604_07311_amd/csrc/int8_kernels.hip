@@ -310,7 +310,8 @@ __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
   const int yrow = kYHalf ? ((tid >> 5) << 3) | ((tid >> 1) & 7) : crow;
   const int yofs = kYHalf ? 8 * (2 * ((tid >> 4) & 1) + (tid & 1)) : cofs;
   const bool ythr = kYHalf || tid < 2 * kI8BN;
-  const int st0 = 2 * g.kb0, st1 = 2 * g.kb1;
+  constexpr int kStepsPerBlock = kI8K / kI8Step;
+  const int st0 = kStepsPerBlock * g.kb0, st1 = kStepsPerBlock * g.kb1;
   i32x4 rx[NL][S];
   ychunk_t ry[NL][S];
   // loads of step st into register set Q (steps past the last re-read it;
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(kThreads, 1) void int8_gemm(Int8GemmArgs<OffT> g) {
   auto fetch = [&](auto qc, int st) {
     constexpr int Q = decltype(qc)::value;
     st = st < st1 ? st : st1 - 1;
-    const int64_t blk = (int64_t)(st / 2), half = 32 * (st % 2);
+    const int64_t blk = (int64_t)(st / kStepsPerBlock), half = kI8Step * (st % kStepsPerBlock);
 #pragma unroll
     for (int t2 = 0; t2 < S; ++t2) {
       rx[Q][t2] = *global(reinterpret_cast<const i32x4*>(xb + t2 * xplane + blk * (kI8BM * kI8K) + crow * kI8K +
