@@ -49,7 +49,7 @@ def used_offsets(lay: synth.Strided) -> np.ndarray:
     return off
 
 
-class GpuRunner:
+class DeviceRunner:
     """Runs problems through the C ABI on cuda:0 with flat device buffers,
     so any strides (negative, zero, padded) can be used."""
 

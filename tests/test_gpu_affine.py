@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import GpuRunner, check_fp32, check_fp64, round_inputs
+from tests.famlies_testutil import DeviceRunner, check_fp32, check_fp64, round_inputs
 
 pytestmark = pytest.mark.gpu
 
@@ -20,7 +20,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def gpu():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 def _problem(la, lb, lc, ext, orders, seed, alpha=1.0, beta=0.5):

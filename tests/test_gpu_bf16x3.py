@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import GpuRunner, bf16x3_bound, gamma, round_inputs, used_offsets
+from tests.famlies_testutil import DeviceRunner, bf16x3_bound, gamma, round_inputs, used_offsets
 
 pytestmark = pytest.mark.gpu
 
@@ -16,7 +16,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def gpu():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 def _d_prod(p):

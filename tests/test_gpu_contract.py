@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import (GpuRunner, check_fp32, check_fp64, gamma, oracle_full,
+from tests.famlies_testutil import (DeviceRunner, check_fp32, check_fp64, gamma, oracle_full,
                                     round_inputs, used_offsets)
 
 pytestmark = pytest.mark.gpu
@@ -23,7 +23,7 @@ def note(msg):
 def gpu():
     import torch
     assert torch.cuda.is_available(), "GPU test run without a GPU"
-    return GpuRunner()
+    return DeviceRunner()
 
 
 def _parity(gpu, p, dtype, alpha=None, beta=None):

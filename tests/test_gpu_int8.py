@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import GpuRunner, U64, gamma, used_offsets
+from tests.famlies_testutil import DeviceRunner, U64, gamma, used_offsets
 from tests.test_oracle import _random_roles_problem
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +31,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def runner():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 @pytest.mark.parametrize("seed", range(24))

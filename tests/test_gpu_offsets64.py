@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import GpuRunner, bf16x3_bound, check_fp32, check_fp64, gamma, round_inputs, used_offsets
+from tests.famlies_testutil import DeviceRunner, bf16x3_bound, check_fp32, check_fp64, gamma, round_inputs, used_offsets
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def gpu():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 @pytest.fixture(params=["64", "e32"])

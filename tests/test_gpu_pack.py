@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.famlies_testutil import GpuRunner, check_fp32, check_fp64, round_inputs, used_offsets
+from tests.famlies_testutil import DeviceRunner, check_fp32, check_fp64, round_inputs, used_offsets
 
 pytestmark = pytest.mark.gpu
 
@@ -19,7 +19,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def gpu():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 def _forced_handle(fm, tmp_path, p, dtype, compute, bm, split=1):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.famlies_testutil import GpuRunner, check_fp32, check_fp64, oracle_full, round_inputs, used_offsets
+from tests.famlies_testutil import DeviceRunner, check_fp32, check_fp64, oracle_full, round_inputs, used_offsets
 
 pytestmark = pytest.mark.gpu
 
@@ -17,7 +17,7 @@ def note(msg):
 
 @pytest.fixture(scope="module")
 def gpu():
-    return GpuRunner()
+    return DeviceRunner()
 
 
 def _problems():
