@@ -65,6 +65,30 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
 #pragma unroll
       for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
     }
+  } else if constexpr (G::E == 8) {
+    // Two 4-k chunks per row (16-deep slices).  Rows 16 apart share banks at
+    // the 12-word pitch, so the 32 lanes of one store would collide in
+    // pairs: lanes 16..31 of each half-wave write their chunks in the other
+    // order (each store then covers the 64 banks once).  Both chunks are
+    // split before either is written.
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    uint32_t p[2][2][NS];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      split2<NS>(gg.template val<EDGE, S>(4 * q, k0, kend), gg.template val<EDGE, S>(4 * q + 1, k0, kend), p[q][0]);
+      split2<NS>(gg.template val<EDGE, S>(4 * q + 2, k0, kend), gg.template val<EDGE, S>(4 * q + 3, k0, kend),
+                 p[q][1]);
+    }
+    const bool rot = (threadIdx.x >> 4) & 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = gg.lds_index(4 * (rot ? 1 - i : i), kSplitLD<NS>);
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        const u32x2 w = {rot ? p[1 - i][0][t] : p[i][0][t], rot ? p[1 - i][1][t] : p[i][1][t]};
+        *reinterpret_cast<u32x2*>(tiles + t * tile_elems + idx) = w;
+      }
+    }
   } else {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
