@@ -66,11 +66,11 @@ __device__ __forceinline__ void store_split(const G& gg, __bf16* tiles, int tile
       for (int t = 0; t < NS; ++t) *reinterpret_cast<uint32_t*>(tiles + t * tile_elems + idx) = p[t];
     }
   } else if constexpr (G::E == 8) {
-    // Two 4-k chunks per row (16-deep slices).  Rows 16 apart share banks at
-    // the 12-word pitch, so the 32 lanes of one store would collide in
-    // pairs: lanes 16..31 of each half-wave write their chunks in the other
-    // order (each store then covers the 64 banks once).  Both chunks are
-    // split before either is written.
+    // Two 4-k chunks per row (16-deep slices): both are split before either
+    // is written, and lanes 16..31 of each half-wave write them in the other
+    // order.  Measured on the bf16x6 ring: 2-3 % faster than splitting and
+    // writing chunk by chunk, with the same LDS bank-conflict count (those
+    // conflicts are not these stores').
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     uint32_t p[2][2][NS];
 #pragma unroll
