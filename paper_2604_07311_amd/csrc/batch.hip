@@ -7,7 +7,8 @@
 // workgroups: problems are spread over the XCDs by estimated cost (so a
 // problem's tiles share one L2; a problem larger than a quarter of an XCD's
 // share is cut into runs of tiles first), and each XCD's items form one queue,
-// largest problems first with a problem's tiles consecutive.  The
+// the costliest items (largest padded K) first with a problem's tiles
+// consecutive.  The
 // workgroups of an XCD take items from its queue with an atomic counter, so
 // a problem's tiles run side by side and no workgroup idles while its queue
 // has work (longest-processing-time-first, decided as the launch runs).  The
@@ -371,9 +372,10 @@ famlies_status batch_plan_make(famlies_handle_s* h, famlies_plan_s** out, int dt
     const auto& js = per_prob[(size_t)u.prob];
     for (size_t i = u.first; i < u.first + u.count; ++i) xjobs[(size_t)x].push_back(js[i]);
   }
-  // 2) each XCD's queue: largest problems first, a problem's tiles
-  //    consecutive, so the workgroups that draw them run them side by side
-  //    and the problem's operand panels are read once into the XCD's L2
+  // 2) each XCD's queue: the costliest items first (item cost: the padded
+  //    tile's MFMA work, so largest K first), a problem's tiles consecutive,
+  //    so the workgroups that draw them run them side by side and the
+  //    problem's operand panels are read once into the XCD's L2
   std::vector<BatchItem> items;
   std::vector<int32_t> q_start(kXcds + 1, 0);
   for (int x = 0; x < kXcds; ++x) {
